@@ -1,0 +1,357 @@
+"""Oracle for the PairDiag method: plain, slow, obviously correct, CPU only.
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package.  It shares no code with the GPU
+library (the C part lives in pd_oracle.c and is built with gcc by build()).
+Everything is FP64.
+
+Functions and the passages they follow:
+  binom, basis_alg1, hash_index, unhash, index_bsearch   Sec. 3.1-3.2, Eq. extcmn, Alg. conversion, Eq. hash
+  sigma, sigma_sampled, dense_h                           Sec. 3.3, Eq. hamiltonian2, Eq. diagonal
+  dense_ground                                            E0 as the lowest eigenvalue of the explicit H
+  lanczos_ground                                          Sec. 3.4, Alg. lanczos, full reorthogonalisation,
+                                                          restart with the ground Ritz vector, Eq. convergence
+  occupations, monopole_min                               Sec. 4.3 outputs N_Occup and Monopole_Min
+  richardson_evb                                          constant-G check (Richardson equations, eigenvalue form)
+  pbcs_vector                                             number-projected product start vector (warm start)
+  mlp_*                                                   FP64 reference of the warm-start network
+
+Parity status: every function here is pinned by a not-gpu test (paper tables,
+closed forms, invariants, brute force), except the trained network weights,
+which are not a function of the paper ("parity unpinned": judged by the
+iterations they save).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pd_oracle.c")
+_SO = os.path.join(_HERE, "_pd_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile pd_oracle.c with gcc (OpenMP over rows)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        u64, i64, i32, dbl = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        P = ctypes.c_void_p
+        L.or_binom.restype, L.or_binom.argtypes = u64, [i32, i32]
+        L.or_next_state.restype, L.or_next_state.argtypes = u64, [u64]
+        L.or_basis_alg1.restype, L.or_basis_alg1.argtypes = i64, [i32, i32, P, i64]
+        L.or_hash.restype, L.or_hash.argtypes = i64, [u64]
+        L.or_unhash.restype, L.or_unhash.argtypes = u64, [i64, i32]
+        L.or_index_bsearch.restype, L.or_index_bsearch.argtypes = i64, [P, i64, u64]
+        L.or_sigma_rows.restype = i32
+        L.or_sigma_rows.argtypes = [i32, i32, P, P, P, i64, i32, P, P, i64, i64]
+        L.or_sigma_sampled.restype = i32
+        L.or_sigma_sampled.argtypes = [i32, i32, P, P, i64, P, P, i64, P]
+        L.or_dense_h.restype, L.or_dense_h.argtypes = i32, [i32, i32, P, P, P, i64, P]
+        L.or_occupations.restype, L.or_occupations.argtypes = None, [i32, P, i64, P, P]
+        L.or_num_threads.restype, L.or_num_threads.argtypes = i32, []
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+# ---------------------------------------------------------------- basis (Sec. 3.1-3.2)
+
+def binom(n: int, m: int) -> int:
+    """C^m_n of Eq. extcmn (0 for n < m)."""
+    return int(lib().or_binom(n, m))
+
+
+def next_state(s: int) -> int:
+    return int(lib().or_next_state(s))
+
+
+def basis_alg1(omega: int, n: int) -> np.ndarray:
+    """All C^n_omega states in generation order by the '01' inversion iteration."""
+    d = binom(omega, n)
+    out = np.empty(d, dtype=np.uint64)
+    got = lib().or_basis_alg1(omega, n, _p(out), d)
+    if got != d:
+        raise RuntimeError(f"basis generation produced {got} states, expected {d}")
+    return out
+
+
+def hash_index(s: int) -> int:
+    """0-based f(|s>) - 1 of Eq. hash."""
+    return int(lib().or_hash(int(s)))
+
+
+def unhash(r: int, n: int) -> int:
+    return int(lib().or_unhash(int(r), n))
+
+
+def index_bsearch(basis: np.ndarray, t: int) -> int:
+    return int(lib().or_index_bsearch(_p(basis), basis.size, int(t)))
+
+
+# ---------------------------------------------------------------- H (Sec. 3.3)
+
+def _check_h(omega, eps, V):
+    eps = _f64(eps)
+    V = _f64(V)
+    assert eps.shape == (omega,) and V.shape == (omega, omega)
+    return eps, V
+
+
+def sigma(omega: int, n: int, eps, V, basis: np.ndarray, x, index_mode: str = "bsearch",
+          rows: tuple[int, int] | None = None) -> np.ndarray:
+    """y = H x over rows [r0, r1) (all rows by default).  index_mode 'bsearch'
+    (independent path) or 'hash' (the paper's fast path, used for timing)."""
+    eps, V = _check_h(omega, eps, V)
+    x = _f64(x)
+    r0, r1 = rows if rows is not None else (0, basis.size)
+    y = np.empty(r1 - r0)
+    rc = lib().or_sigma_rows(omega, n, _p(eps), _p(V), _p(basis), basis.size,
+                             1 if index_mode == "hash" else 0, _p(x), _p(y), r0, r1)
+    if rc != 0:
+        raise RuntimeError("hop target missing from the basis")
+    return y
+
+
+def sigma_sampled(omega: int, n: int, eps, V, x, rows) -> np.ndarray:
+    """(H x)[r] for the listed ranks r, with no stored basis (inverse hash + hash)."""
+    eps, V = _check_h(omega, eps, V)
+    x = _f64(x)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.empty(rows.size)
+    rc = lib().or_sigma_sampled(omega, n, _p(eps), _p(V), binom(omega, n), _p(x), _p(rows),
+                                rows.size, _p(y))
+    if rc != 0:
+        raise RuntimeError("bad row or hop target")
+    return y
+
+
+def dense_h(omega: int, n: int, eps, V, basis: np.ndarray | None = None) -> np.ndarray:
+    eps, V = _check_h(omega, eps, V)
+    if basis is None:
+        basis = basis_alg1(omega, n)
+    d = basis.size
+    if d > 13000:
+        raise ValueError("dense H only for small spaces")
+    H = np.zeros((d, d))
+    if lib().or_dense_h(omega, n, _p(eps), _p(V), _p(basis), d, _p(H)) != 0:
+        raise RuntimeError("hop target missing from the basis")
+    return H
+
+
+def occupations(omega: int, basis: np.ndarray, psi) -> np.ndarray:
+    """<N_i> = 2 <S+_i S-_i> (Sec. 4.3, N_Occup)."""
+    psi = _f64(psi)
+    occ = np.empty(omega)
+    lib().or_occupations(omega, _p(basis), basis.size, _p(psi), _p(occ))
+    return occ
+
+
+def monopole_min(omega: int, n: int, eps, V) -> float:
+    """Minimum diagonal element (Monopole_Min, the Hartree-Fock energy):
+    the sum of the n smallest pair energies 2 eps_i + V_ii (Eq. diagonal)."""
+    eps, V = _check_h(omega, eps, V)
+    d = np.sort(2.0 * eps + np.diag(V))
+    return float(d[:n].sum())
+
+
+def _normalise_sign(psi: np.ndarray) -> np.ndarray:
+    psi = psi / np.linalg.norm(psi)
+    return -psi if psi.sum() < 0 else psi
+
+
+def dense_ground(omega: int, n: int, eps, V):
+    """E0, psi0 and <N_i> from the explicit matrix (library eigensolver)."""
+    basis = basis_alg1(omega, n)
+    H = dense_h(omega, n, eps, V, basis)
+    w, Z = np.linalg.eigh(H)
+    psi = _normalise_sign(Z[:, 0])
+    return float(w[0]), psi, occupations(omega, basis, psi), w
+
+
+# ---------------------------------------------------------------- Lanczos (Sec. 3.4)
+
+def lanczos_ground(omega: int, n: int, eps, V, krylov: int = 50, tol: float = 1e-10,
+                   max_restarts: int = 200, start=None, restart: bool = True,
+                   basis: np.ndarray | None = None, index_mode: str = "bsearch"):
+    """Restarted Lanczos of Alg. lanczos with Gram-Schmidt against all stored
+    vectors (applied twice), Ritz pairs of the tridiagonal L, restart from the
+    ground-state Ritz vector, stop when |beta_1/alpha_1| <= tol (Eq. convergence).
+
+    start: None -> [1, 0, ..., 0] (the paper's default), else a vector.
+    Returns dict(E0, psi, occ, iterations, restarts, residual)."""
+    eps, V = _check_h(omega, eps, V)
+    if basis is None:
+        basis = basis_alg1(omega, n)
+    d = basis.size
+    H = lambda v: sigma(omega, n, eps, V, basis, v, index_mode)
+    if start is None:
+        p = np.zeros(d)
+        p[0] = 1.0
+    else:
+        p = _f64(start).copy()
+    m = min(krylov, d)
+    iterations = 0
+    residual = math.inf
+    theta = math.nan
+    for cycle in range(max_restarts + 1):
+        Q = np.zeros((m, d))
+        alpha = np.zeros(m)
+        beta = np.zeros(m)
+        k_used = m
+        for i in range(m):
+            Q[i] = p / np.linalg.norm(p)
+            p = H(Q[i])
+            iterations += 1
+            alpha[i] = Q[i] @ p
+            p = p - alpha[i] * Q[i] - (beta[i - 1] * Q[i - 1] if i > 0 else 0.0)
+            for _ in range(2):
+                p = p - Q[: i + 1].T @ (Q[: i + 1] @ p)
+            beta[i] = np.linalg.norm(p)
+            if i == 0:
+                residual = beta[0] / max(abs(alpha[0]), 1e-300)
+                if cycle > 0 and residual <= tol:
+                    theta = alpha[0]
+                    psi = Q[0]
+                    return _finish(omega, basis, psi, theta, iterations, cycle, residual)
+            if beta[i] <= 1e-14 * max(abs(alpha[i]), 1.0):
+                k_used = i + 1
+                break
+        T = np.diag(alpha[:k_used]) + np.diag(beta[: k_used - 1], 1) + np.diag(beta[: k_used - 1], -1)
+        w, Z = np.linalg.eigh(T)
+        theta = w[0]
+        psi = Q[:k_used].T @ Z[:, 0]
+        if k_used < m or not restart:
+            r = H(psi / np.linalg.norm(psi))
+            t = psi / np.linalg.norm(psi)
+            residual = np.linalg.norm(r - (t @ r) * t) / abs(t @ r)
+            return _finish(omega, basis, psi, t @ r, iterations, cycle, residual)
+        p = psi
+    return _finish(omega, basis, psi, theta, iterations, max_restarts, residual)
+
+
+def _finish(omega, basis, psi, theta, iterations, restarts, residual):
+    psi = _normalise_sign(psi)
+    return dict(E0=float(theta), psi=psi, occ=occupations(omega, basis, psi),
+                iterations=iterations, restarts=restarts, residual=float(residual))
+
+
+# ---------------------------------------------------------------- Richardson (constant G)
+
+def richardson_evb(eps, g: float, n: int, steps: int = 400, newton_iters: int = 30) -> float:
+    """Ground-state energy (and the u_i) for eps_i distinct and constant V_ij = -g,
+    i.e. pair energies e_i = 2 eps_i, from the Richardson equations in eigenvalue form.
+
+    Unknowns u_i = g sum_alpha 1/(e_i - E_alpha) satisfy
+        u_i^2 = u_i + g sum_{j != i} (u_i - u_j)/(e_i - e_j),     sum_i u_i = n,
+    and E0 = sum_i e_i u_i - g n (Omega - n + 1).
+    Continued in g from 0 (u = 1 on the n lowest levels) with Newton steps."""
+    e = 2.0 * _f64(eps)
+    omega = e.size
+    order = np.argsort(e)
+    u = np.zeros(omega)
+    u[order[:n]] = 1.0
+    diff = e[:, None] - e[None, :]
+    np.fill_diagonal(diff, np.inf)
+    inv = 1.0 / diff                     # 1/(e_i - e_j), 0 on the diagonal
+    for s in range(1, steps + 1):
+        gs = g * s / steps
+        for _ in range(newton_iters):
+            du = u[:, None] - u[None, :]
+            F = u * u - u - gs * (du * inv).sum(axis=1)
+            J = gs * inv.copy()
+            np.fill_diagonal(J, 2.0 * u - 1.0 - gs * inv.sum(axis=1))
+            step = np.linalg.solve(J, -F)
+            u = u + step
+            if np.max(np.abs(step)) < 1e-15:
+                break
+    return float(e @ u - g * n * (omega - n + 1)), u
+
+
+# ---------------------------------------------------------------- warm start
+
+def pbcs_vector(omega: int, n: int, logits, basis: np.ndarray | None = None) -> np.ndarray:
+    """Number-projected product state: psi_k proportional to prod_{i in occ(k)} z_i,
+    z_i = exp(l_i / 2), normalised, computed term by term in log space."""
+    if basis is None:
+        basis = basis_alg1(omega, n)
+    l = _f64(logits)
+    bits = ((basis[:, None] >> np.arange(omega, dtype=np.uint64)[None, :]) & np.uint64(1)).astype(np.float64)
+    logpsi = 0.5 * (bits @ l)
+    psi = np.exp(logpsi - logpsi.max())
+    return psi / np.linalg.norm(psi)
+
+
+def gelu_tanh(x):
+    """GELU, tanh form (Hendrycks & Gimpel 2016)."""
+    c = math.sqrt(2.0 / math.pi)
+    return 0.5 * x * (1.0 + np.tanh(c * (x + 0.044715 * x ** 3)))
+
+
+def gelu_tanh_grad(x):
+    c = math.sqrt(2.0 / math.pi)
+    t = np.tanh(c * (x + 0.044715 * x ** 3))
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * c * (1.0 + 3 * 0.044715 * x * x)
+
+
+def mlp_forward(params, X):
+    """X (B x in) -> logits (B x out); params = [W1, b1, W2, b2, W3, b3], W as (in x out).
+    Hidden layers use GELU, the output layer is linear."""
+    W1, b1, W2, b2, W3, b3 = [_f64(p) for p in params]
+    X = _f64(X)
+    z1 = X @ W1 + b1
+    h1 = gelu_tanh(z1)
+    z2 = h1 @ W2 + b2
+    h2 = gelu_tanh(z2)
+    out = h2 @ W3 + b3
+    return out, (X, z1, h1, z2, h2)
+
+
+def mlp_loss(logits, target_half_occ):
+    """mean over all entries of (sigmoid(l) - <N_i>/2)^2."""
+    s = 1.0 / (1.0 + np.exp(-_f64(logits)))
+    r = s - _f64(target_half_occ)
+    return float(np.mean(r * r)), 2.0 * r * s * (1.0 - s) / r.size
+
+
+def mlp_backward(params, cache, dout):
+    W1, b1, W2, b2, W3, b3 = [_f64(p) for p in params]
+    X, z1, h1, z2, h2 = cache
+    dW3 = h2.T @ dout
+    db3 = dout.sum(axis=0)
+    dh2 = dout @ W3.T
+    dz2 = dh2 * gelu_tanh_grad(z2)
+    dW2 = h1.T @ dz2
+    db2 = dz2.sum(axis=0)
+    dh1 = dz2 @ W2.T
+    dz1 = dh1 * gelu_tanh_grad(z1)
+    dW1 = X.T @ dz1
+    db1 = dz1.sum(axis=0)
+    return [dW1, db1, dW2, db2, dW3, db3]
