@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X: prints one JSON line.
+
+Workload: the large random family at Omega=32, n=16 (601,080,390 states,
+256 pair hops per row), eps ~ U[0, 32), G_ij = 0.3(1 + 0.2u), seed 0.  One
+step is one ground-state solve (pd_lanczos_ground: basis by unranking, sigma,
+recurrence, full reorthogonalisation, tridiagonal solve, restarts, FP64
+acceptance, occupations) in mixed precision (FP32 products, FP64 everything
+else) to an FP64-checked residual of 1e-10, from a seeded random start.
+
+value = sigma non-zeros generated per second of the timed solves (whole job).
+Also reported: time-to-E0 for plain FP64 and mixed precision, per-product
+sigma rates, the roofline of the dominant kernel (the FP32 sigma) from its
+HIP-event durations inside the timed region, and the oracle's CPU rate on a
+bounded sample of rows of the same instance.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--omega", type=int, default=32)
+    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--krylov", type=int, default=20)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 time-to-E0 solve")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size in rows (0: auto)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sigma-reps", type=int, default=5)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel_tag, workload_tag):
+    """Per-launch HBM bytes of a kernel from a committed rocprofv3 counter summary
+    (profiles/<kernel>_<workload>_counters.txt, lines 'key: value'), or None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_{workload_tag}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(om, n, eps, V, rows_req):
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    d = math.comb(om, n)
+    K = n * (om - n)
+    x = np.ones(d)              # values do not change the work; the full vector is needed for the gathers
+    r0 = d // 3
+    rows = rows_req or 200000
+    t = time.perf_counter()
+    oracle.sigma_block(om, n, eps, V, x, r0, r0 + 2000)      # warm caches / threads
+    t = time.perf_counter()
+    oracle.sigma_block(om, n, eps, V, x, r0, r0 + rows)
+    dt = time.perf_counter() - t
+    if not rows_req and dt < 10.0:
+        rows = int(rows * min(20.0 / max(dt, 1e-3), 200.0))
+        rows = min(rows, d - r0)
+        t = time.perf_counter()
+        oracle.sigma_block(om, n, eps, V, x, r0, r0 + rows)
+        dt = time.perf_counter() - t
+    return dict(value=rows * K / dt, unit="nnz/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"hash-search oracle sigma (states by '01' inversion, targets by the hash) over "
+                       f"{rows} consecutive rows from rank {r0} of the same Omega={om}, n={n} instance "
+                       f"({rows * K:.3e} non-zeros, {dt:.1f} s)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the multi-GPU path is not part of this build "
+              "(see the sharding plan in DESIGN.md); use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2001_01978_amd import inputs, pairdiag
+
+    torch.cuda.set_device(0)
+    om, n = args.omega, args.n
+    _, _, eps, V = inputs.c5_instance(om, n, seed=0)
+    K = n * (om - n)
+    basis = pairdiag.Basis(om, n, store_states=False)
+    D = basis.dim
+    log(f"workload omega={om} n={n} dim={D} hops/row={K}")
+
+    # ---- per-product sigma rates (separate buffers, same stream)
+    sig = {}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        x = torch.empty(D, dtype=dt, device="cuda").uniform_(-1, 1)
+        y = torch.empty_like(x)
+        basis.sigma(eps, V, x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.sigma_reps):
+            basis.sigma(eps, V, x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / args.sigma_reps
+        es = 4 if name == "f32" else 8
+        balg = D * (K * es + 2 * es)
+        sig[name] = dict(ms=t * 1e3, nnz_per_s=D * K / t, alg_GBps=balg / t / 1e9, alg_bytes=balg)
+        log(f"sigma {name}: {t*1e3:.2f} ms  {D*K/t:.3e} nnz/s  {balg/t/1e9:.0f} GB/s algorithmic")
+        del x, y
+    torch.cuda.empty_cache()
+
+    common = dict(krylov=args.krylov, tol=args.tol, start="random", seed=1, want_psi=False)
+    nb_mixed = pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f32")
+    ws = pairdiag.device_buffer(nb_mixed)
+
+    def solve(precision):
+        return pairdiag.lanczos_ground(basis, eps, V, precision=precision, workspace=ws, **common)
+
+    for w in range(args.warmup):
+        r = solve("f32")
+        log(f"warmup {w}: E0={r.E0:.12f} products={r.iterations} ({r.iterations_f32} f32) {r.seconds:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for k in range(args.steps):
+        r = solve("f32")
+        results.append(r)
+        log(f"step {k}: E0={r.E0:.12f} rho={r.residual:.2e} products={r.iterations} ({r.iterations_f32} f32) "
+            f"{r.seconds:.2f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nnz = sum(r.iterations for r in results) * D * K
+    value = nnz / elapsed
+    mixed = results[-1]
+    n32 = sum(r.iterations_f32 for r in results)
+    s32 = sum(r.sigma_seconds_f32 for r in results)
+    avg32 = s32 / max(n32, 1)
+    balg32 = D * (K * 4 + 8)
+    achieved = balg32 / avg32 / 1e9 if n32 else None
+
+    plain = None
+    if not args.no_plain:
+        r64 = solve("f64")
+        plain = r64
+        log(f"plain f64: E0={r64.E0:.12f} products={r64.iterations} {r64.seconds:.2f} s")
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(om, n, eps, V, args.cpu_rows)
+        log(f"cpu baseline: {cpu['value']:.3e} nnz/s on {cpu['cores']} threads")
+
+    traffic = traffic_from_profiles("sigma_f32", f"omega{om}_n{n}")
+    out = {
+        "metric": "sigma nonzeros/s + HBM GB/s; time-to-E0 at Omega=32,n=16, plain vs mixed vs warm",
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded SplitMix64 instance, eps~U[0,32), G_ij=0.3(1+0.2u))",
+        "config": {"workload": f"ground state, Omega={om}, n={n}, dim={D}, mixed precision, "
+                               f"krylov={args.krylov}, tol={args.tol:g}",
+                   "omega": om, "n": n, "dim": D, "hops_per_row": K, "krylov": args.krylov},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+                     "traffic": traffic,
+                     "kernel": "sigma_kernel<uint32,float,16>",
+                     "algorithmic_bytes_per_launch": balg32,
+                     "avg_launch_ms": avg32 * 1e3},
+        "cpu_baseline": cpu,
+        "time_to_E0_s": {"mixed": mixed.seconds, "f64": plain.seconds if plain else None, "warm": None},
+        "E0": {"mixed": mixed.E0, "f64": plain.E0 if plain else None,
+               "rel_diff": abs(mixed.E0 - plain.E0) / abs(plain.E0) if plain else None},
+        "products": {"mixed": mixed.iterations, "mixed_f32": mixed.iterations_f32,
+                     "f64": plain.iterations if plain else None},
+        "sigma": sig,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

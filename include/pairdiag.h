@@ -1,0 +1,177 @@
+/*
+ * pairdiag.h -- C ABI of the MI355X (gfx950) library for exact diagonalisation
+ * of general pairing Hamiltonians in the seniority-zero space.
+ *
+ * The Hamiltonian is Eq. hamiltonian2 of Liu & Qi, "PairDiag: an exact
+ * diagonalization program for solving general pairing Hamiltonians":
+ *     H = sum_i (2 eps_i + V_ii) S+_i S-_i + sum_{i != j} V_ij S+_i S-_j
+ * on omega doubly-degenerate orbits holding n pairs (the paper's m pairs in n
+ * orbits, Sec. 3.1).  V is the paper's pairing matrix P_F taken literally
+ * (attractive pairing has V_ij < 0).
+ *
+ * Conventions shared by every entry point:
+ *   - Device memory is owned by the caller (any allocator; the Python binding
+ *     uses torch tensors).  The library never allocates device memory; each
+ *     object states the bytes it needs through a *_bytes query.  Host arrays
+ *     are read during the call only.
+ *   - Arguments are validated before any device work; invalid arguments
+ *     return PD_EINVAL (or PD_ERANGE / PD_ENOMEM) and leave outputs untouched.
+ *     A HIP failure returns PD_EDEVICE.  pd_last_error() gives a thread-local
+ *     message for the last failure.
+ *   - Work is issued on the given stream (0 = the null stream).  Entry points
+ *     that return host scalars synchronise that stream before returning;
+ *     the others are asynchronous and stream-ordered.
+ *   - Basis ranks are 0-based: rank = f(|i>) - 1 with the hash of Sec. 3.2.
+ *     The basis order is the ascending order of Tab. data and Alg. conversion.
+ *   - Vectors are indexed by rank, length dim = C(omega, n) (Eq. extcmn).
+ */
+#ifndef PAIRDIAG_H
+#define PAIRDIAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PD_OK = 0,
+    PD_EINVAL = 1,   /* bad argument (sizes, non-finite or non-symmetric V, null pointer) */
+    PD_ERANGE = 2,   /* valid but unsupported size (e.g. dim does not fit the index type) */
+    PD_ENOMEM = 3,   /* caller buffer smaller than the matching *_bytes query */
+    PD_EDEVICE = 4,  /* HIP runtime error; see pd_last_error() */
+    PD_ENOCONV = 5   /* iteration stopped before the tolerance; outputs hold the best iterate */
+} pd_status;
+
+typedef enum { PD_F64 = 0, PD_F32 = 1 } pd_dtype;
+
+/* Start vectors of the Lanczos iteration (Sec. 3.4: the paper's default is e_1). */
+typedef enum {
+    PD_START_E1 = 0,      /* [1, 0, ..., 0]: the paper's Vector_Initialize */
+    PD_START_HF = 1,      /* basis state with the n smallest 2 eps_i + V_ii */
+    PD_START_RANDOM = 2,  /* x_k = 2 u_k - 1, u_k from SplitMix64 (seed, counter k) */
+    PD_START_USER = 3     /* caller vector x0_dev (any norm, must be non-zero) */
+} pd_start;
+
+const char *pd_version(void);
+const char *pd_status_str(pd_status s);
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char *pd_last_error(void);
+
+/* ------------------------------------------------------------------ basis
+ * Sec. 3.1 (basis generation, Alg. conversion) and Sec. 3.2 (Eq. hash).
+ * A basis handle describes the space (omega, n) and carries a small
+ * coefficient block used by pd_sigma.  With store_states != 0 the library also
+ * writes the ascending array of occupation bitstrings (uint64, bit i =
+ * orbit i) into the caller buffer; sigma and the Lanczos driver never read it
+ * (they recover states from ranks on the fly), so large spaces may skip it.
+ * Limits: 1 <= omega <= 62, 0 <= n <= omega (Sec. 3.1: fewer than 63 orbits).
+ */
+typedef struct pd_basis_s *pd_basis;
+
+/* Device bytes pd_basis_create needs; 0 for invalid (omega, n). */
+size_t pd_basis_bytes(int omega, int n, int store_states);
+/* Number of states C(omega, n); 0 for invalid (omega, n). */
+int64_t pd_dimension(int omega, int n);
+/* Builds the handle in *out.  dev_buf must stay valid while the handle lives. */
+pd_status pd_basis_create(int omega, int n, int store_states, void *dev_buf, size_t bytes,
+                          hipStream_t stream, pd_basis *out);
+/* NULL-safe; never frees dev_buf. */
+void pd_basis_destroy(pd_basis b);
+pd_status pd_basis_info(pd_basis b, int *omega, int *n, int64_t *dim);
+/* Device pointer of the stored state array (NULL if store_states was 0). */
+const uint64_t *pd_basis_states(pd_basis b);
+/* ranks_dev[q] = rank of states_dev[q], or -1 if it is not an n-pair state
+ * of the omega orbits.  Both arrays are device memory of `count` entries. */
+pd_status pd_basis_rank(pd_basis b, const uint64_t *states_dev, int64_t count,
+                        int64_t *ranks_dev, hipStream_t stream);
+/* states_dev[q] = state of rank ranks_dev[q]; ranks must lie in [0, dim). */
+pd_status pd_basis_unrank(pd_basis b, const int64_t *ranks_dev, int64_t count,
+                          uint64_t *states_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------ sigma
+ * y = H x, the matrix-free product of Sec. 3.3: every non-zero element is
+ * generated from the pair hops |j> = S+_E S-_O |i> and located by its rank.
+ * eps: host, omega doubles.  V: host, omega*omega doubles, row-major, exactly
+ * symmetric and finite.  x, y: device vectors of dim elements of dtype dt
+ * (PD_F64: double gathers and accumulation; PD_F32: float gathers, float
+ * accumulation, coefficients rounded to float).  x and y must not overlap.
+ * The coefficients are kept in the handle's device block: when they differ
+ * from the previous call on this handle they are uploaded on `stream` and
+ * the stream is synchronised; otherwise the call is fully asynchronous.
+ * Calls with different coefficients on one handle must be issued in order
+ * (one stream, or synchronised by the caller).
+ */
+pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
+                   const void *x_dev, void *y_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------ Lanczos
+ * Restarted, fully reorthogonalised Lanczos (Sec. 3.4, Alg. lanczos): Krylov
+ * vectors are orthogonalised against all stored vectors (classical
+ * Gram-Schmidt applied twice), the lowest Ritz pair of the krylov x krylov
+ * tridiagonal matrix comes from Sturm bisection and inverse iteration, and
+ * the iteration restarts from the
+ * ground-state Ritz vector.  Convergence (Eq. convergence): the restarted
+ * vector q has rho = ||H q - (q^T H q) q|| / |q^T H q| <= tol; rho is computed
+ * with an FP64 product.  mode 1 stops after the first cycle (no restart).
+ */
+typedef struct {
+    int krylov;        /* vectors per cycle (Lanc_Limit); 2..64; default 50 */
+    double tol;        /* Lanc_Error; default 1e-10 */
+    int max_restarts;  /* cycles after the first; default 1000 */
+    int mode;          /* 0 restarted (default), 1 single cycle */
+    int start;         /* pd_start; default PD_START_E1 */
+    uint64_t seed;     /* PD_START_RANDOM stream */
+    int precision;     /* PD_F64 (default) or PD_F32: FP32 products for Krylov steps
+                          k >= 2 of every cycle; the first step of each cycle, all
+                          dot products, the recurrence, the reorthogonalisation, the
+                          tridiagonal solve and the Ritz vectors stay FP64 */
+    int verbose;       /* 1: one line per cycle on stderr */
+} pd_lanczos_opts;
+
+typedef struct {
+    int iterations;      /* products H q (FP64 + FP32) */
+    int iterations_f32;  /* of which FP32 */
+    int restarts;        /* cycles after the first */
+    int converged;       /* 1 if rho <= tol */
+    double residual;     /* final rho */
+    double monopole_min; /* smallest diagonal element (Monopole_Min, Sec. 4.3) */
+    double seconds;      /* wall time of the call */
+    double sigma_seconds_f64;  /* summed device time of the FP64 products (HIP events) */
+    double sigma_seconds_f32;  /* summed device time of the FP32 products (HIP events) */
+} pd_lanczos_info;
+
+void pd_lanczos_default_opts(pd_lanczos_opts *o);
+/* Device workspace bytes for pd_lanczos_ground with these options. */
+size_t pd_lanczos_workspace_bytes(pd_basis b, const pd_lanczos_opts *o);
+/* Ground state of H.  Outputs: *E0 (= q^T H q of the returned vector),
+ * psi0_dev (device, dim doubles, optional: normalised, sum(psi) >= 0),
+ * occ (host, omega doubles, optional: <N_i> = 2 <S+_i S-_i>, Sec. 4.3 N_Occup),
+ * info (optional).  x0_dev: device start vector for PD_START_USER, else NULL.
+ * Returns PD_ENOCONV (outputs filled) if max_restarts is reached first.
+ * Synchronises `stream`. */
+pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V,
+                            const pd_lanczos_opts *o, void *work_dev, size_t work_bytes,
+                            const double *x0_dev, double *E0, double *psi0_dev, double *occ,
+                            pd_lanczos_info *info, hipStream_t stream);
+
+/* <N_i> = 2 sum_k psi_k^2 [orbit i occupied in state k] for a device vector
+ * psi (dim doubles, not renormalised); occ_host receives omega doubles.
+ * work_dev needs pd_occupations_workspace_bytes(b).  Synchronises `stream`. */
+size_t pd_occupations_workspace_bytes(pd_basis b);
+pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size_t work_bytes,
+                         double *occ_host, hipStream_t stream);
+
+/* ------------------------------------------------------------------ host utility
+ * Lowest eigenpair of the m x m symmetric tridiagonal matrix with diagonal
+ * alpha[0..m) and off-diagonal beta[0..m-1) (the Lanczos matrix L of
+ * Alg. lanczos), 1 <= m <= 64; y receives the unit eigenvector with y[0] >= 0.
+ * Host arrays, no device work.  Returns 0, or a negative value on bad input. */
+int pd_tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAIRDIAG_H */

@@ -7,7 +7,7 @@ Everything is FP64.
 
 Functions and the passages they follow:
   binom, basis_alg1, hash_index, unhash, index_bsearch   Sec. 3.1-3.2, Eq. extcmn, Alg. conversion, Eq. hash
-  sigma, sigma_sampled, dense_h                           Sec. 3.3, Eq. hamiltonian2, Eq. diagonal
+  sigma, sigma_sampled, row_terms, dense_h                Sec. 3.3, Eq. hamiltonian2, Eq. diagonal
   dense_ground                                            E0 as the lowest eigenvalue of the explicit H
   lanczos_ground                                          Sec. 3.4, Alg. lanczos, full reorthogonalisation,
                                                           restart with the ground Ritz vector, Eq. convergence
@@ -64,6 +64,10 @@ def lib():
         L.or_sigma_sampled.restype = i32
         L.or_sigma_sampled.argtypes = [i32, i32, P, P, i64, P, P, i64, P]
         L.or_dense_h.restype, L.or_dense_h.argtypes = i32, [i32, i32, P, P, P, i64, P]
+        L.or_sigma_block.restype = i32
+        L.or_sigma_block.argtypes = [i32, i32, P, P, i64, P, i64, i64, P]
+        L.or_row_terms.restype = dbl
+        L.or_row_terms.argtypes = [i32, i32, P, P, i64, P, P, ctypes.POINTER(i64)]
         L.or_occupations.restype, L.or_occupations.argtypes = None, [i32, P, i64, P, P]
         L.or_num_threads.restype, L.or_num_threads.argtypes = i32, []
         _lib = L
@@ -151,6 +155,35 @@ def sigma_sampled(omega: int, n: int, eps, V, x, rows) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("bad row or hop target")
     return y
+
+
+def sigma_block(omega: int, n: int, eps, V, x, r0: int, r1: int) -> np.ndarray:
+    """(H x)[r0:r1] as the paper's program computes it: states by the '01'
+    inversion, targets by the hash (no stored basis; x is the full vector)."""
+    eps, V = _check_h(omega, eps, V)
+    x = _f64(x)
+    y = np.empty(r1 - r0)
+    if lib().or_sigma_block(omega, n, _p(eps), _p(V), binom(omega, n), _p(x), r0, r1, _p(y)) != 0:
+        raise RuntimeError("bad row range")
+    return y
+
+
+def row_terms(omega: int, n: int, eps, V, rows):
+    """For each rank r: the diagonal H_rr, the hop targets and their elements
+    (Sec. 3.3), from the hash alone.  Returns (diag[c], targets[c, K], coefs[c, K]),
+    K = n(omega - n), so that (H x)[r] = diag*x[r] + sum(coefs * x[targets])."""
+    eps, V = _check_h(omega, eps, V)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    K = n * (omega - n)
+    diag = np.empty(rows.size)
+    tg = np.empty((rows.size, max(K, 1)), dtype=np.int64)
+    cf = np.empty((rows.size, max(K, 1)))
+    cnt = ctypes.c_int64()
+    for q, r in enumerate(rows):
+        diag[q] = lib().or_row_terms(omega, n, _p(eps), _p(V), int(r), _p(tg[q]), _p(cf[q]), ctypes.byref(cnt))
+        if cnt.value != K:
+            raise RuntimeError(f"bad row {r}")
+    return diag, tg[:, :K], cf[:, :K]
 
 
 def dense_h(omega: int, n: int, eps, V, basis: np.ndarray | None = None) -> np.ndarray:

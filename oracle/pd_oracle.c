@@ -198,6 +198,59 @@ int or_sigma_sampled(int omega, int n, const double *eps, const double *V,
     return bad ? -1 : 0;
 }
 
+/* The non-zero terms of row `row` (Sec. 3.3) without a stored basis: returns
+ * the diagonal element, writes the n(omega-n) hop targets (hash of Sec. 3.2)
+ * and their elements V_EO in the order O ascending, E ascending.  Returns the
+ * number of hops in *count (-1 on a bad row). */
+double or_row_terms(int omega, int n, const double *eps, const double *V, int64_t row,
+                    int64_t *targets, double *coefs, int64_t *count)
+{
+    cmn_init();
+    uint64_t s = or_unhash(row, n);
+    if (s == ~0ull) { *count = -1; return 0.0; }
+    double diag = 0.0;
+    for (int i = 0; i < omega; ++i)
+        if ((s >> i) & 1ull) diag += 2.0 * eps[i] + V[i * omega + i];
+    int64_t q = 0;
+    for (int O = 0; O < omega; ++O) {
+        if (!((s >> O) & 1ull)) continue;
+        for (int E = 0; E < omega; ++E) {
+            if ((s >> E) & 1ull) continue;
+            uint64_t t = (s & ~(1ull << O)) | (1ull << E);
+            targets[q] = or_hash(t);
+            coefs[q] = V[E * omega + O];
+            ++q;
+        }
+    }
+    *count = q;
+    return diag;
+}
+
+/* y[r - r0] = (H x)[r] for r in [r0, r1) the way the paper's program runs:
+ * states by the '01' inversion from the block start, targets by the hash.
+ * Each thread takes a contiguous chunk and finds its first state from the
+ * inverse hash.  Used for CPU timing. */
+int or_sigma_block(int omega, int n, const double *eps, const double *V, int64_t dim,
+                   const double *x, int64_t r0, int64_t r1, double *y)
+{
+    int bad = 0;
+    cmn_init();
+    const int64_t chunk = 16384;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t c0 = r0; c0 < r1; c0 += chunk) {
+        int64_t c1 = c0 + chunk < r1 ? c0 + chunk : r1;
+        uint64_t s = or_unhash(c0, n);
+        if (s == ~0ull) { bad = 1; continue; }
+        for (int64_t r = c0; r < c1; ++r) {
+            int b = 0;
+            y[r - r0] = row_value(omega, eps, V, s, NULL, dim, 1, x, r, &b);
+            bad |= b;
+            if (r + 1 < c1) s = or_next_state(s);
+        }
+    }
+    return bad ? -1 : 0;
+}
+
 /* Explicit dense H (row-major dim x dim), zero-initialised by the caller. */
 int or_dense_h(int omega, int n, const double *eps, const double *V,
                const uint64_t *basis, int64_t dim, double *H)

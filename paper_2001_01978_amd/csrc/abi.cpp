@@ -1,0 +1,333 @@
+// C ABI entry points (include/pairdiag.h): argument validation, handle
+// lifecycle and dispatch to the kernels.  No entry point allocates device
+// memory; all of it comes from caller buffers sized by the *_bytes queries.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <algorithm>
+
+#include "pd_internal.h"
+
+namespace pd {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+pd_status fail(pd_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+const char *last_error() { return g_err; }
+
+pd_status pack_coefficients(int omega, int n, const double *eps, const double *V, CoefBlock *out) {
+    if (omega < 1 || omega > kMaxOmega) return fail(PD_EINVAL, "omega=%d outside [1, %d]", omega, kMaxOmega);
+    if (n < 0 || n > omega) return fail(PD_EINVAL, "n=%d outside [0, omega]", n);
+    if (!eps || !V) return fail(PD_EINVAL, "eps and V must be host arrays");
+    std::memset(out, 0, sizeof(CoefBlock));
+    for (int i = 0; i < omega; ++i)
+        if (!std::isfinite(eps[i])) return fail(PD_EINVAL, "eps[%d] is not finite", i);
+    for (int i = 0; i < omega; ++i)
+        for (int j = 0; j < omega; ++j) {
+            double v = V[i * omega + j];
+            if (!std::isfinite(v)) return fail(PD_EINVAL, "V[%d][%d] is not finite", i, j);
+            if (v != V[j * omega + i]) return fail(PD_EINVAL, "V is not symmetric at (%d, %d)", i, j);
+        }
+    double s64 = 0.0;
+    float s32 = 0.0f;
+    for (int i = 0; i < omega; ++i) {
+        double d = 2.0 * eps[i] + V[i * omega + i];
+        out->d64[i] = d;
+        out->d32[i] = (float)d;
+        s64 += d;
+        s32 += (float)d;
+    }
+    out->dsum64 = s64;
+    out->dsum32 = s32;
+    for (int i = 0; i < omega * omega; ++i) {
+        out->V64[i] = V[i];
+        out->V32[i] = (float)V[i];
+    }
+    // V is stored with row stride omega: V[b*omega + a]
+    return PD_OK;
+}
+
+size_t lanczos_workspace_bytes(int64_t dim, const pd_lanczos_opts *o);
+pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_opts *o, void *work,
+                      size_t work_bytes, const double *x0, double *E0_out, double *psi0, double *occ_out,
+                      pd_lanczos_info *info_out, hipStream_t s);
+
+namespace {
+
+bool valid_space(int omega, int n) { return omega >= 1 && omega <= kMaxOmega && n >= 0 && n <= omega; }
+
+pd_status check_sigma_range(pd_basis b) {
+    int nn = std::min(b->n, b->omega - b->n);
+    if (nn > kMaxSigmaPairs)
+        return fail(PD_ERANGE, "min(n, omega-n)=%d exceeds %d (dim %lld)", nn, kMaxSigmaPairs, (long long)b->dim);
+    return PD_OK;
+}
+
+// Device memory check: turns host or foreign pointers, and device ranges that
+// run past the end of their allocation, into PD_EINVAL before any kernel runs.
+pd_status check_device_ptr(const void *p, const char *what, size_t bytes = 0) {
+    if (!p) return fail(PD_EINVAL, "%s is NULL", what);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PD_EINVAL, "%s is not device memory (%s)", what, hipGetErrorString(e));
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(PD_EINVAL, "%s is not device memory", what);
+    if (bytes) {
+        hipDeviceptr_t base = nullptr;
+        size_t size = 0;
+        e = hipMemGetAddressRange(&base, &size, const_cast<void *>(p));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PD_EINVAL, "%s: cannot query its allocation (%s)", what, hipGetErrorString(e));
+        }
+        const char *b0 = static_cast<const char *>(base), *pp = static_cast<const char *>(p);
+        if (pp + bytes > b0 + size)
+            return fail(PD_EINVAL, "%s: %zu bytes needed past %p, allocation ends %zu bytes after it", what, bytes,
+                        p, (size_t)(b0 + size - pp));
+    }
+    return PD_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+pd_status check_basis(pd_basis b) {
+    if (!b) return fail(PD_EINVAL, "basis handle is NULL");
+    return PD_OK;
+}
+
+}  // namespace
+}  // namespace pd
+
+using namespace pd;
+
+extern "C" {
+
+const char *pd_version(void) { return "pairdiag-gfx950 0.1"; }
+
+const char *pd_status_str(pd_status s) {
+    switch (s) {
+        case PD_OK: return "PD_OK";
+        case PD_EINVAL: return "PD_EINVAL";
+        case PD_ERANGE: return "PD_ERANGE";
+        case PD_ENOMEM: return "PD_ENOMEM";
+        case PD_EDEVICE: return "PD_EDEVICE";
+        case PD_ENOCONV: return "PD_ENOCONV";
+    }
+    return "PD_UNKNOWN";
+}
+
+const char *pd_last_error(void) { return last_error(); }
+
+int64_t pd_dimension(int omega, int n) {
+    if (!valid_space(omega, n)) return 0;
+    return (int64_t)binom_host(omega, n);
+}
+
+size_t pd_basis_bytes(int omega, int n, int store_states) {
+    if (!valid_space(omega, n)) return 0;
+    size_t b = kCoefBytes;
+    if (store_states) b += align256((size_t)binom_host(omega, n) * sizeof(uint64_t));
+    return b;
+}
+
+pd_status pd_basis_create(int omega, int n, int store_states, void *dev_buf, size_t bytes, hipStream_t stream,
+                          pd_basis *out) {
+    if (!out) return fail(PD_EINVAL, "out is NULL");
+    if (!valid_space(omega, n)) return fail(PD_EINVAL, "invalid space omega=%d n=%d", omega, n);
+    size_t need = pd_basis_bytes(omega, n, store_states);
+    if (bytes < need) return fail(PD_ENOMEM, "basis buffer %zu bytes, need %zu", bytes, need);
+    pd_status st = check_device_ptr(dev_buf, "dev_buf", need);
+    if (st != PD_OK) return st;
+    if (reinterpret_cast<uintptr_t>(dev_buf) & 255) return fail(PD_EINVAL, "dev_buf must be 256-byte aligned");
+    pd_basis b = new (std::nothrow) pd_basis_s;
+    if (!b) return fail(PD_ENOMEM, "host allocation failed");
+    b->omega = omega;
+    b->n = n;
+    b->dim = (int64_t)binom_host(omega, n);
+    b->coef = reinterpret_cast<CoefBlock *>(dev_buf);
+    b->states = store_states ? reinterpret_cast<uint64_t *>(static_cast<unsigned char *>(dev_buf) + kCoefBytes)
+                             : nullptr;
+    b->has_coef = 0;
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+    if (b->states) {
+        hipError_t e = launch_basis_build(omega, n, b->dim, b->states, stream);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(PD_EDEVICE, "basis build: %s", hipGetErrorString(e));
+        }
+    }
+    *out = b;
+    return PD_OK;
+}
+
+void pd_basis_destroy(pd_basis b) { delete b; }
+
+pd_status pd_basis_info(pd_basis b, int *omega, int *n, int64_t *dim) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (omega) *omega = b->omega;
+    if (n) *n = b->n;
+    if (dim) *dim = b->dim;
+    return PD_OK;
+}
+
+const uint64_t *pd_basis_states(pd_basis b) { return b ? b->states : nullptr; }
+
+pd_status pd_basis_rank(pd_basis b, const uint64_t *states_dev, int64_t count, int64_t *ranks_dev,
+                        hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (count < 0) return fail(PD_EINVAL, "count < 0");
+    if (count == 0) return PD_OK;
+    if ((st = check_device_ptr(states_dev, "states_dev", count * 8)) != PD_OK) return st;
+    if ((st = check_device_ptr(ranks_dev, "ranks_dev", count * 8)) != PD_OK) return st;
+    hipError_t e = launch_basis_rank(b->omega, b->n, states_dev, count, ranks_dev, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "rank: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+pd_status pd_basis_unrank(pd_basis b, const int64_t *ranks_dev, int64_t count, uint64_t *states_dev,
+                          hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (count < 0) return fail(PD_EINVAL, "count < 0");
+    if (count == 0) return PD_OK;
+    if ((st = check_device_ptr(states_dev, "states_dev", count * 8)) != PD_OK) return st;
+    if ((st = check_device_ptr(ranks_dev, "ranks_dev", count * 8)) != PD_OK) return st;
+    hipError_t e = launch_basis_unrank(b->omega, b->n, ranks_dev, count, states_dev, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "unrank: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt, const void *x_dev, void *y_dev,
+                   hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (dt != PD_F64 && dt != PD_F32) return fail(PD_EINVAL, "dtype %d", (int)dt);
+    if ((st = check_sigma_range(b)) != PD_OK) return st;
+    CoefBlock blk;
+    if ((st = pack_coefficients(b->omega, b->n, eps, V, &blk)) != PD_OK) return st;
+    const size_t es = dt == PD_F64 ? 8 : 4;
+    if ((st = check_device_ptr(x_dev, "x_dev", b->dim * es)) != PD_OK) return st;
+    if ((st = check_device_ptr(y_dev, "y_dev", b->dim * es)) != PD_OK) return st;
+    if (overlap(x_dev, b->dim * es, y_dev, b->dim * es)) return fail(PD_EINVAL, "x and y overlap");
+    // Upload only when the coefficients change; the copy completes before returning.
+    if (!b->has_coef || std::memcmp(&blk, &b->host_coef, sizeof(CoefBlock)) != 0) {
+        hipError_t e = hipMemcpyAsync(b->coef, &blk, sizeof(CoefBlock), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail(PD_EDEVICE, "coefficient upload: %s", hipGetErrorString(e));
+        b->host_coef = blk;
+        b->has_coef = 1;
+    }
+    hipError_t e = launch_sigma(b->omega, b->n, b->dim, b->coef, dt, x_dev, y_dev, stream, blk.dsum64, blk.dsum32);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "sigma: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+void pd_lanczos_default_opts(pd_lanczos_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->krylov = 50;
+    o->tol = 1e-10;
+    o->max_restarts = 1000;
+    o->mode = 0;
+    o->start = PD_START_E1;
+    o->seed = 0;
+    o->precision = PD_F64;
+    o->verbose = 0;
+}
+
+static pd_status check_opts(const pd_lanczos_opts *o) {
+    if (!o) return fail(PD_EINVAL, "opts is NULL");
+    if (o->krylov < 2 || o->krylov > 64) return fail(PD_EINVAL, "krylov=%d outside [2, 64]", o->krylov);
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(PD_EINVAL, "tol must be finite and >= 0");
+    if (o->max_restarts < 0) return fail(PD_EINVAL, "max_restarts < 0");
+    if (o->mode != 0 && o->mode != 1) return fail(PD_EINVAL, "mode must be 0 or 1");
+    if (o->start < PD_START_E1 || o->start > PD_START_USER) return fail(PD_EINVAL, "start=%d", o->start);
+    if (o->precision != PD_F64 && o->precision != PD_F32) return fail(PD_EINVAL, "precision=%d", o->precision);
+    return PD_OK;
+}
+
+size_t pd_lanczos_workspace_bytes(pd_basis b, const pd_lanczos_opts *o) {
+    if (!b || check_opts(o) != PD_OK) return 0;
+    return lanczos_workspace_bytes(b->dim, o);
+}
+
+pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V, const pd_lanczos_opts *o,
+                            void *work_dev, size_t work_bytes, const double *x0_dev, double *E0, double *psi0_dev,
+                            double *occ, pd_lanczos_info *info, hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if ((st = check_opts(o)) != PD_OK) return st;
+    if (!E0) return fail(PD_EINVAL, "E0 is NULL");
+    if ((st = check_sigma_range(b)) != PD_OK) return st;
+    CoefBlock blk;
+    if ((st = pack_coefficients(b->omega, b->n, eps, V, &blk)) != PD_OK) return st;
+    size_t need = lanczos_workspace_bytes(b->dim, o);
+    if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+    if ((st = check_device_ptr(work_dev, "work_dev", need)) != PD_OK) return st;
+    if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
+    if (o->start == PD_START_USER) {
+        if ((st = check_device_ptr(x0_dev, "x0_dev", b->dim * 8)) != PD_OK) return st;
+    }
+    if (psi0_dev) {
+        if ((st = check_device_ptr(psi0_dev, "psi0_dev", b->dim * 8)) != PD_OK) return st;
+        if (overlap(psi0_dev, b->dim * 8, work_dev, work_bytes)) return fail(PD_EINVAL, "psi0 overlaps workspace");
+    }
+    return lanczos_run(b, blk, o, work_dev, work_bytes, x0_dev, E0, psi0_dev, occ, info, stream);
+}
+
+size_t pd_occupations_workspace_bytes(pd_basis b) {
+    if (!b) return 0;
+    return align256(partial_doubles() * sizeof(double)) + align256(64 * sizeof(double));
+}
+
+pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size_t work_bytes, double *occ_host,
+                         hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (!occ_host) return fail(PD_EINVAL, "occ_host is NULL");
+    size_t need = pd_occupations_workspace_bytes(b);
+    if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+    if ((st = check_device_ptr(psi_dev, "psi_dev", b->dim * 8)) != PD_OK) return st;
+    if ((st = check_device_ptr(work_dev, "work_dev", need)) != PD_OK) return st;
+    double *partials = static_cast<double *>(work_dev);
+    double *occ_dev = reinterpret_cast<double *>(static_cast<unsigned char *>(work_dev) +
+                                                 align256(partial_doubles() * sizeof(double)));
+    hipError_t e = launch_occupations(b->omega, b->n, b->dim, psi_dev, partials, occ_dev, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(occ_host, occ_dev, b->omega * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "occupations: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+int pd_tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y) {
+    if (!alpha || !theta || !y || (m > 1 && !beta)) return -1;
+    return tridiag_lowest(m, alpha, beta, theta, y);
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+// Restarted, fully reorthogonalised Lanczos driver (Sec. 3.4, Alg. lanczos).
+//
+// One cycle builds up to m = krylov orthonormal vectors q_1..q_m in the
+// workspace.  Step k: p = H q_k; c = Q^T p (so alpha_k = c_k); p -= Q c;
+// c' = Q^T p; p -= Q c' (Gram-Schmidt against every stored vector, applied
+// twice; this also removes alpha_k q_k and beta_{k-1} q_{k-1}); beta_k = ||p||;
+// q_{k+1} = p / beta_k.  After the cycle the lowest Ritz pair of the
+// tridiagonal L = tridiag(beta, alpha, beta) gives psi = Q y, the start of the
+// next cycle.  The first step of every cycle measures the residual of its
+// start vector, |beta_1 / alpha_1| = ||H q - (q^T H q) q|| / |q^T H q|
+// (Eq. convergence), and stops when it is below tol.
+//
+// Mixed precision: steps k >= 2 of a cycle may run the product in FP32 on an
+// FP32 copy of q_k.  Step 1 (the residual and alpha_1 = q^T H q of the restart
+// vector) is always FP64, so the FP32 error only enters the correction,
+// whose size shrinks with the residual; every stored quantity, dot product
+// and update is FP64.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+#include "pd_internal.h"
+
+namespace pd {
+
+namespace {
+
+struct Layout {
+    size_t coef = 0, scal = 0, partials = 0, Q = 0, p = 0, w = 0, x32 = 0, y32 = 0, total = 0;
+    int64_t ld = 0;
+    int m = 0;
+};
+
+constexpr int kScalars = 512;  // doubles: c[64], c2[64], nrm2, sum, occ[64]
+constexpr int kOffC = 0, kOffC2 = 64, kOffNrm = 192, kOffSum = 193, kOffOcc = 256;
+
+Layout layout_for(int64_t dim, int krylov, int precision) {
+    Layout L;
+    L.m = (int)std::min<int64_t>(krylov, dim);
+    L.ld = (dim + 63) & ~int64_t(63);
+    size_t off = 0;
+    L.coef = off;
+    off += kCoefBytes;
+    L.scal = off;
+    off += align256(kScalars * sizeof(double));
+    L.partials = off;
+    off += align256(partial_doubles() * sizeof(double));
+    L.Q = off;
+    off += align256((size_t)L.m * L.ld * sizeof(double));
+    L.p = off;
+    off += align256((size_t)L.ld * sizeof(double));
+    L.w = off;
+    off += align256((size_t)L.ld * sizeof(double));
+    if (precision == PD_F32) {
+        L.x32 = off;
+        off += align256((size_t)L.ld * sizeof(float));
+        L.y32 = off;
+        off += align256((size_t)L.ld * sizeof(float));
+    }
+    L.total = off;
+    return L;
+}
+
+struct Dev {
+    hipStream_t s;
+    double *scal;
+    double host[kScalars];
+    hipError_t fetch(int off, int count) {
+        hipError_t e = hipMemcpyAsync(host + off, scal + off, count * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+    // one synchronisation for two ranges
+    hipError_t fetch2(int off1, int count1, int off2, int count2) {
+        hipError_t e = hipMemcpyAsync(host + off1, scal + off1, count1 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(host + off2, scal + off2, count2 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+};
+
+}  // namespace
+
+size_t lanczos_workspace_bytes(int64_t dim, const pd_lanczos_opts *o) {
+    return layout_for(dim, o->krylov, o->precision).total;
+}
+
+pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_opts *o, void *work,
+                      size_t work_bytes, const double *x0, double *E0_out, double *psi0, double *occ_out,
+                      pd_lanczos_info *info_out, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int omega = b->omega, n = b->n;
+    const int64_t dim = b->dim;
+    Layout L = layout_for(dim, o->krylov, o->precision);
+    if (work_bytes < L.total)
+        return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
+    unsigned char *base = static_cast<unsigned char *>(work);
+    CoefBlock *coef = reinterpret_cast<CoefBlock *>(base + L.coef);
+    double *scal = reinterpret_cast<double *>(base + L.scal);
+    double *partials = reinterpret_cast<double *>(base + L.partials);
+    double *Q = reinterpret_cast<double *>(base + L.Q);
+    double *p = reinterpret_cast<double *>(base + L.p);
+    double *w = reinterpret_cast<double *>(base + L.w);
+    float *x32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.x32) : nullptr;
+    float *y32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.y32) : nullptr;
+    const int64_t ld = L.ld;
+    const int m = L.m;
+    const double dsum64 = host_coef.dsum64;
+    const float dsum32 = host_coef.dsum32;
+
+    pd_lanczos_info info;
+    std::memset(&info, 0, sizeof(info));
+    {
+        std::vector<double> dd(host_coef.d64, host_coef.d64 + omega);
+        std::sort(dd.begin(), dd.end());
+        double mm = 0.0;
+        for (int i = 0; i < n; ++i) mm += dd[i];
+        info.monopole_min = mm;
+    }
+    double dscale = 0.0;
+    for (int i = 0; i < omega; ++i) dscale = std::max(dscale, std::fabs(host_coef.d64[i]));
+    if (dscale == 0.0) dscale = 1.0;
+
+    PD_HIP(hipMemcpyAsync(coef, &host_coef, sizeof(CoefBlock), hipMemcpyHostToDevice, s));
+    PD_HIP(hipStreamSynchronize(s));
+    Dev dev{s, scal, {}};
+
+    // ---- start vector into w
+    switch (o->start) {
+        case PD_START_E1:
+            PD_HIP(launch_fill_unit(dim, 0, w, s));
+            break;
+        case PD_START_HF: {
+            std::vector<int> idx(omega);
+            for (int i = 0; i < omega; ++i) idx[i] = i;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int a, int c) { return host_coef.d64[a] < host_coef.d64[c]; });
+            uint64_t st = 0;
+            for (int i = 0; i < n; ++i) st |= 1ull << idx[i];
+            int64_t r = 0;
+            int j = 0;
+            for (int q = 0; q < omega; ++q)
+                if ((st >> q) & 1ull) r += (int64_t)binom_host(q, ++j);
+            PD_HIP(launch_fill_unit(dim, r, w, s));
+            break;
+        }
+        case PD_START_RANDOM:
+            PD_HIP(launch_fill_random(o->seed, dim, w, s));
+            break;
+        case PD_START_USER:
+            PD_HIP(launch_copy(x0, dim, w, s));
+            break;
+        default:
+            return fail(PD_EINVAL, "unknown start %d", o->start);
+    }
+    PD_HIP(launch_norm_sum(w, dim, partials, scal + kOffNrm, scal + kOffSum, s));
+    PD_HIP(dev.fetch(kOffNrm, 1));
+    if (!(dev.host[kOffNrm] > 0.0) || !std::isfinite(dev.host[kOffNrm]))
+        return fail(PD_EINVAL, "start vector has zero or non-finite norm");
+    {
+        double sc = 1.0 / std::sqrt(dev.host[kOffNrm]);
+        PD_HIP(launch_scale(w, dim, sc, Q, x32, s));
+    }
+
+    // HIP events around every product: its device time, read after the step's sync
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    PD_HIP(hipEventCreate(&ev.a));
+    PD_HIP(hipEventCreate(&ev.b));
+
+    std::vector<double> alpha(m), beta(m), y(m);
+    double theta = 0.0, residual = INFINITY, e0 = NAN;
+    bool converged = false;
+    bool final_check = false;  // this cycle only measures its start vector
+    int cycle = 0;
+    for (cycle = 0;; ++cycle) {
+        int m_eff = m;
+        for (int k = 0; k < m; ++k) {
+            double *qk = Q + (size_t)k * ld;
+            const bool f32_step = x32 && k >= 1;
+            PD_HIP(hipEventRecord(ev.a, s));
+            if (f32_step) {
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, x32, y32, s, dsum64, dsum32));
+                PD_HIP(hipEventRecord(ev.b, s));
+                PD_HIP(launch_f32_to_f64(y32, dim, p, s));
+                ++info.iterations_f32;
+            } else {
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32));
+                PD_HIP(hipEventRecord(ev.b, s));
+            }
+            ++info.iterations;
+            PD_HIP(launch_gemvt(Q, ld, k + 1, dim, p, partials, scal + kOffC, s));
+            PD_HIP(launch_update_gemvt(Q, ld, k + 1, dim, scal + kOffC, p, p, partials, scal + kOffC2, s));
+            PD_HIP(launch_update_norm(Q, ld, k + 1, dim, scal + kOffC2, p, p, partials, scal + kOffNrm, s));
+            PD_HIP(dev.fetch2(kOffC + k, 1, kOffNrm, 1));
+            {
+                float ms = 0.0f;
+                PD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                (f32_step ? info.sigma_seconds_f32 : info.sigma_seconds_f64) += 1e-3 * ms;
+            }
+            alpha[k] = dev.host[kOffC + k];
+            beta[k] = std::sqrt(std::max(dev.host[kOffNrm], 0.0));
+            if (k == 0) {
+                e0 = alpha[0];
+                residual = beta[0] / std::max(std::fabs(alpha[0]), 1e-3 * dscale);
+                if (o->verbose)
+                    std::fprintf(stderr, "[pairdiag] cycle %d  E=%.15g  rho=%.3e  products=%d\n", cycle, e0,
+                                 residual, info.iterations);
+                if (residual <= o->tol) converged = true;
+                if (converged || final_check) break;
+            }
+            double tnorm = 0.0;
+            for (int i = 0; i <= k; ++i) tnorm = std::max(tnorm, std::fabs(alpha[i]) + beta[i]);
+            if (beta[k] <= 1e-14 * std::max(tnorm, 1e-300)) {
+                m_eff = k + 1;  // invariant subspace: the Ritz pair is exact
+                break;
+            }
+            if (k + 1 < m) {
+                PD_HIP(launch_scale(p, dim, 1.0 / beta[k], Q + (size_t)(k + 1) * ld, x32, s));
+            }
+        }
+        if (converged || final_check) break;
+        if (tridiag_lowest(m_eff, alpha.data(), beta.data(), &theta, y.data()) != 0)
+            return fail(PD_EDEVICE, "tridiagonal eigensolver failed (m=%d)", m_eff);
+        PD_HIP(launch_combine(Q, ld, m_eff, dim, y.data(), w, partials, scal + kOffNrm, scal + kOffSum, s));
+        PD_HIP(dev.fetch(kOffNrm, 1));
+        double nr = std::sqrt(dev.host[kOffNrm]);
+        if (!(nr > 0.0)) return fail(PD_EDEVICE, "Ritz vector vanished");
+        PD_HIP(launch_scale(w, dim, 1.0 / nr, Q, x32, s));
+        // Mode 1 (no restart) and the last allowed cycle only measure the Ritz vector next.
+        if (o->mode == 1 || cycle >= o->max_restarts) final_check = true;
+    }
+    info.restarts = cycle;
+    info.converged = converged ? 1 : 0;
+    info.residual = residual;
+
+    // ---- outputs from q_1 (normalised FP64 vector whose Rayleigh quotient is e0)
+    PD_HIP(launch_norm_sum(Q, dim, partials, scal + kOffNrm, scal + kOffSum, s));
+    PD_HIP(dev.fetch(kOffNrm, 2));
+    double sign = dev.host[kOffSum] < 0.0 ? -1.0 : 1.0;
+    if (psi0) PD_HIP(launch_scale(Q, dim, sign, psi0, nullptr, s));
+    if (occ_out) {
+        PD_HIP(launch_occupations(omega, n, dim, Q, partials, scal + kOffOcc, s));
+        PD_HIP(dev.fetch(kOffOcc, omega));
+        for (int i = 0; i < omega; ++i) occ_out[i] = dev.host[kOffOcc + i];
+    }
+    PD_HIP(hipStreamSynchronize(s));
+    *E0_out = e0;
+    info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out) *info_out = info;
+    if (!converged && o->mode == 0)
+        return fail(PD_ENOCONV, "not converged after %d restarts (rho=%.3e)", cycle, residual);
+    return PD_OK;
+}
+
+}  // namespace pd

@@ -1,0 +1,136 @@
+// Internal declarations of the pairdiag HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <cstddef>
+
+#include "pairdiag.h"
+
+namespace pd {
+
+// ---------------------------------------------------------------- binomials
+// C(p, k) for 0 <= p, k < 64 with C = 0 for p < k (the paper's extension of
+// Eq. extcmn), built at compile time by Pascal's rule.  All values fit uint64.
+struct BinomTable {
+    uint64_t v[64][64];
+    constexpr BinomTable() : v() {
+        for (int p = 0; p < 64; ++p) {
+            v[p][0] = 1;
+            for (int k = 1; k <= p; ++k) v[p][k] = v[p - 1][k - 1] + (k <= p - 1 ? v[p - 1][k] : 0);
+        }
+    }
+};
+static constexpr BinomTable kBinomHost{};
+static __constant__ BinomTable g_binom = BinomTable();
+
+inline uint64_t binom_host(int p, int k) {
+    if (p < 0 || k < 0 || p > 63 || k > 63 || p < k) return 0;
+    return kBinomHost.v[p][k];
+}
+
+// Coefficient block: pair energies and couplings in FP64 and FP32.
+//   d[i] = 2 eps_i + V_ii (diagonal pair energy, Eq. diagonal)
+//   V[b*omega + a] = V_ba (Eq. hamiltonian2), V_ii kept but unused by hops
+constexpr int kMaxOmega = 62;
+struct CoefBlock {
+    double d64[64];
+    double dsum64;
+    double pad0[7];
+    float d32[64];
+    float dsum32;
+    float pad1[15];
+    double V64[kMaxOmega * kMaxOmega];
+    float V32[kMaxOmega * kMaxOmega];
+};
+constexpr size_t kCoefBytes = (sizeof(CoefBlock) + 255) & ~size_t(255);
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+pd_status fail(pd_status s, const char *fmt, ...);
+const char *last_error();
+
+#define PD_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::pd::fail(PD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Validates (omega, n, eps, V) and packs the coefficient block.
+pd_status pack_coefficients(int omega, int n, const double *eps, const double *V, CoefBlock *out);
+
+}  // namespace pd
+
+struct pd_basis_s {
+    int omega;
+    int n;
+    int64_t dim;
+    uint64_t *states;        // device, dim entries, or nullptr
+    pd::CoefBlock *coef;     // device, per-handle block for pd_sigma
+    int device;
+    int has_coef;            // coef holds host_coef
+    pd::CoefBlock host_coef; // last block uploaded by pd_sigma
+};
+
+namespace pd {
+
+// ---------------------------------------------------------------- launchers
+// basis.hip
+hipError_t launch_basis_build(int omega, int n, int64_t dim, uint64_t *states, hipStream_t s);
+hipError_t launch_basis_rank(int omega, int n, const uint64_t *states, int64_t count,
+                             int64_t *ranks, hipStream_t s);
+hipError_t launch_basis_unrank(int omega, int n, const int64_t *ranks, int64_t count,
+                               uint64_t *states, hipStream_t s);
+
+// Largest min(n, omega - n) sigma handles (register width of its hop loop).
+constexpr int kMaxSigmaPairs = 20;
+// sigma.hip: y = H x for dtype dt using coefficients at coef (device).
+// dsum64/dsum32: sum of all pair energies d_i (host copy of the block's dsum).
+hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd_dtype dt,
+                        const void *x, void *y, hipStream_t s, double dsum64, float dsum32);
+
+// vec.hip: Lanczos vector kernels.  Q holds columns of length dim with leading
+// dimension ld (elements).  `partials` is scratch of partial_doubles() doubles.
+int vec_grid();
+size_t partial_doubles();
+// c[j] = sum_i Q[j][i] * p[i], j < ncols; result to c_dev (device doubles).
+hipError_t launch_gemvt(const double *Q, int64_t ld, int ncols, int64_t dim, const double *p,
+                        double *partials, double *c_dev, hipStream_t s);
+// pout = pin - Q c (j < ncols); then c2 = Q^T pout.  pin may equal pout.
+hipError_t launch_update_gemvt(const double *Q, int64_t ld, int ncols, int64_t dim,
+                               const double *c, const double *pin, double *pout,
+                               double *partials, double *c2_dev, hipStream_t s);
+// pout = pin - Q c; nrm2_dev[0] = ||pout||^2.
+hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim,
+                              const double *c, const double *pin, double *pout,
+                              double *partials, double *nrm2_dev, hipStream_t s);
+// Up to 64 doubles passed to a kernel by value.
+struct SmallVec {
+    double v[64];
+};
+// out = sum_j y[j] Q[j] (j < ncols, y on the host); nrm2_dev[0] = ||out||^2, sum_dev[0] = sum(out).
+hipError_t launch_combine(const double *Q, int64_t ld, int ncols, int64_t dim, const double *y_host,
+                          double *out, double *partials, double *nrm2_dev, double *sum_dev,
+                          hipStream_t s);
+// out = x * scale; optional FP32 copy out32.  out may equal x.
+hipError_t launch_scale(const double *x, int64_t dim, double scale, double *out, float *out32,
+                        hipStream_t s);
+// nrm2/sum of a vector.
+hipError_t launch_norm_sum(const double *x, int64_t dim, double *partials, double *nrm2_dev,
+                           double *sum_dev, hipStream_t s);
+hipError_t launch_f32_to_f64(const float *x, int64_t dim, double *out, hipStream_t s);
+hipError_t launch_fill_random(uint64_t seed, int64_t dim, double *out, hipStream_t s);
+hipError_t launch_fill_unit(int64_t dim, int64_t index, double *out, hipStream_t s);
+hipError_t launch_copy(const double *x, int64_t dim, double *out, hipStream_t s);
+// occ[i] (device, omega doubles) = 2 sum_k psi_k^2 [bit i of state k].
+hipError_t launch_occupations(int omega, int n, int64_t dim, const double *psi, double *partials,
+                              double *occ_dev, hipStream_t s);
+
+// tridiag.cpp: lowest eigenpair of the symmetric tridiagonal (alpha, beta).
+int tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y);
+
+}  // namespace pd

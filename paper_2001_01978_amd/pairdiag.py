@@ -1,0 +1,290 @@
+"""Thin Python binding of libpairdiag.so (include/pairdiag.h).
+
+Argument marshalling only: device memory comes from torch tensors, streams
+from torch.cuda, and every computation runs in the HIP library.  There is no
+fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpairdiag.so")
+
+PD_OK, PD_EINVAL, PD_ERANGE, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV = range(6)
+PD_F64, PD_F32 = 0, 1
+START = {"e1": 0, "hf": 1, "random": 2, "user": 3}
+
+
+class PairDiagError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_STATUS = {0: "PD_OK", 1: "PD_EINVAL", 2: "PD_ERANGE", 3: "PD_ENOMEM", 4: "PD_EDEVICE", 5: "PD_ENOCONV"}
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("krylov", ctypes.c_int), ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
+                ("mode", ctypes.c_int), ("start", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("precision", ctypes.c_int), ("verbose", ctypes.c_int)]
+
+
+class LanczosInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("iterations_f32", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("converged", ctypes.c_int), ("residual", ctypes.c_double), ("monopole_min", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("sigma_seconds_f64", ctypes.c_double),
+                ("sigma_seconds_f32", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); the full exported surface of include/pairdiag.h
+P, I, I64, U64, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "pd_version": (ctypes.c_char_p, []),
+    "pd_status_str": (ctypes.c_char_p, [I]),
+    "pd_last_error": (ctypes.c_char_p, []),
+    "pd_basis_bytes": (SZ, [I, I, I]),
+    "pd_dimension": (I64, [I, I]),
+    "pd_basis_create": (I, [I, I, I, P, SZ, P, ctypes.POINTER(P)]),
+    "pd_basis_destroy": (None, [P]),
+    "pd_basis_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I64)]),
+    "pd_basis_states": (P, [P]),
+    "pd_basis_rank": (I, [P, P, I64, P, P]),
+    "pd_basis_unrank": (I, [P, P, I64, P, P]),
+    "pd_sigma": (I, [P, P, P, I, P, P, P]),
+    "pd_lanczos_default_opts": (None, [ctypes.POINTER(LanczosOpts)]),
+    "pd_lanczos_workspace_bytes": (SZ, [P, ctypes.POINTER(LanczosOpts)]),
+    "pd_lanczos_ground": (I, [P, P, P, ctypes.POINTER(LanczosOpts), P, SZ, P, ctypes.POINTER(D), P, P,
+                              ctypes.POINTER(LanczosInfo), P]),
+    "pd_occupations_workspace_bytes": (SZ, [P]),
+    "pd_occupations": (I, [P, P, P, SZ, P, P]),
+    "pd_tridiag_lowest": (I, [I, P, P, ctypes.POINTER(D), P]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libpairdiag.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_01978_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow=()):
+    if status != PD_OK and status not in allow:
+        raise PairDiagError(status, load().pd_last_error().decode())
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_f64(a, shape) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _hp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def device_buffer(nbytes: int, device="cuda"):
+    """Caller-owned device memory for the library (256-byte aligned)."""
+    torch = _torch()
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t, off
+
+
+def dimension(omega: int, n: int) -> int:
+    return int(load().pd_dimension(omega, n))
+
+
+def tridiag_lowest(alpha, beta):
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    m = a.size
+    y = np.empty(m)
+    th = ctypes.c_double()
+    rc = load().pd_tridiag_lowest(m, _hp(a), _hp(b) if b.size else None, ctypes.byref(th), _hp(y))
+    if rc != 0:
+        raise PairDiagError(PD_EINVAL, "tridiag_lowest failed")
+    return th.value, y
+
+
+class Basis:
+    """Handle for the space of n pairs on omega orbits (pd_basis_create)."""
+
+    def __init__(self, omega: int, n: int, store_states: bool = True, device="cuda", stream=None):
+        L = load()
+        nbytes = L.pd_basis_bytes(omega, n, int(store_states))
+        if nbytes == 0:
+            raise PairDiagError(PD_EINVAL, f"invalid space omega={omega} n={n}")
+        self._buf, self._off = device_buffer(nbytes, device)
+        h = ctypes.c_void_p()
+        _check(L.pd_basis_create(omega, n, int(store_states), ctypes.c_void_p(self._buf.data_ptr() + self._off),
+                                 nbytes, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.omega, self.n = omega, n
+        self.dim = dimension(omega, n)
+        self.store_states = store_states
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pd_basis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def states(self):
+        """Device view (int64 bit patterns) of the stored ascending state array."""
+        if not self.store_states:
+            raise RuntimeError("basis was created without stored states")
+        torch = _torch()
+        ptr = load().pd_basis_states(self._h)
+        offset = ptr - self._buf.data_ptr()
+        return self._buf[offset: offset + self.dim * 8].view(torch.int64)
+
+    def rank(self, states, stream=None):
+        torch = _torch()
+        states = states.contiguous()
+        out = torch.empty(states.numel(), dtype=torch.int64, device=states.device)
+        _check(load().pd_basis_rank(self._h, _dptr(states), states.numel(), _dptr(out), _stream(stream)))
+        return out
+
+    def unrank(self, ranks, stream=None):
+        torch = _torch()
+        ranks = ranks.contiguous().to(torch.int64)
+        out = torch.empty(ranks.numel(), dtype=torch.int64, device=ranks.device)
+        _check(load().pd_basis_unrank(self._h, _dptr(ranks), ranks.numel(), _dptr(out), _stream(stream)))
+        return out
+
+    def sigma(self, eps, V, x, y=None, stream=None):
+        """y = H x (pd_sigma); dtype from x (float64 or float32)."""
+        torch = _torch()
+        eps = _host_f64(eps, (self.omega,))
+        V = _host_f64(V, (self.omega, self.omega))
+        if x.dtype == torch.float64:
+            dt = PD_F64
+        elif x.dtype == torch.float32:
+            dt = PD_F32
+        else:
+            raise TypeError("x must be float64 or float32")
+        if x.numel() != self.dim or not x.is_contiguous():
+            raise ValueError("x must be a contiguous vector of length dim")
+        if y is None:
+            y = torch.empty_like(x)
+        _check(load().pd_sigma(self._h, _hp(eps), _hp(V), dt, _dptr(x), _dptr(y), _stream(stream)))
+        return y
+
+    def occupations(self, psi, stream=None):
+        L = load()
+        nb = L.pd_occupations_workspace_bytes(self._h)
+        buf, off = device_buffer(nb, psi.device)
+        occ = np.empty(self.omega)
+        _check(L.pd_occupations(self._h, _dptr(psi), ctypes.c_void_p(buf.data_ptr() + off), nb, _hp(occ),
+                                _stream(stream)))
+        return occ
+
+
+@dataclass
+class GroundState:
+    E0: float
+    psi: object
+    occ: np.ndarray
+    iterations: int
+    iterations_f32: int
+    restarts: int
+    converged: bool
+    residual: float
+    monopole_min: float
+    seconds: float
+    sigma_seconds_f64: float
+    sigma_seconds_f32: float
+    status: int
+
+
+def make_opts(krylov=50, tol=1e-10, max_restarts=1000, mode=0, start="e1", seed=0, precision="f64",
+              verbose=False) -> LanczosOpts:
+    o = LanczosOpts()
+    load().pd_lanczos_default_opts(ctypes.byref(o))
+    o.krylov, o.tol, o.max_restarts, o.mode = krylov, tol, max_restarts, mode
+    o.start = START[start] if isinstance(start, str) else int(start)
+    o.seed = seed
+    o.precision = PD_F32 if precision in ("f32", "mixed", PD_F32) else PD_F64
+    o.verbose = int(verbose)
+    return o
+
+
+def workspace_bytes(basis: Basis, **kw) -> int:
+    o = make_opts(**kw)
+    return int(load().pd_lanczos_workspace_bytes(basis.handle, ctypes.byref(o)))
+
+
+def lanczos_ground(basis: Basis, eps, V, x0=None, want_psi=True, workspace=None, stream=None, **kw) -> GroundState:
+    """Ground state by restarted Lanczos (pd_lanczos_ground)."""
+    torch = _torch()
+    L = load()
+    if x0 is not None:
+        kw["start"] = "user"
+    o = make_opts(**kw)
+    eps = _host_f64(eps, (basis.omega,))
+    V = _host_f64(V, (basis.omega, basis.omega))
+    nb = L.pd_lanczos_workspace_bytes(basis.handle, ctypes.byref(o))
+    if nb == 0:
+        raise PairDiagError(PD_EINVAL, "bad options")
+    if workspace is None:
+        buf, off = device_buffer(nb, basis.device)
+    else:
+        buf, off = workspace
+    psi = torch.empty(basis.dim, dtype=torch.float64, device=basis.device) if want_psi else None
+    occ = np.empty(basis.omega)
+    e0 = ctypes.c_double()
+    info = LanczosInfo()
+    st = L.pd_lanczos_ground(basis.handle, _hp(eps), _hp(V), ctypes.byref(o),
+                             ctypes.c_void_p(buf.data_ptr() + off), nb,
+                             _dptr(x0) if x0 is not None else None, ctypes.byref(e0),
+                             _dptr(psi) if psi is not None else None, _hp(occ), ctypes.byref(info),
+                             _stream(stream))
+    _check(st, allow=(PD_ENOCONV,))
+    return GroundState(E0=e0.value, psi=psi, occ=occ, iterations=info.iterations,
+                       iterations_f32=info.iterations_f32, restarts=info.restarts, converged=bool(info.converged),
+                       residual=info.residual, monopole_min=info.monopole_min, seconds=info.seconds,
+                       sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32, status=st)

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI library: it loads without a GPU, exports every
+symbol declared in include/pairdiag.h, and its host-only logic (sizes,
+validation that happens before any device work, the tridiagonal eigensolver)
+behaves.  No compute call touches a device here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2001_01978_amd import inputs
+from paper_2001_01978_amd import pairdiag as pdg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "pairdiag.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(pd_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = pdg.load()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(pdg.SIGNATURES), set(declared) ^ set(pdg.SIGNATURES)
+
+
+def test_version_and_status_strings():
+    L = pdg.load()
+    assert L.pd_version().startswith(b"pairdiag")
+    for s, name in enumerate(["PD_OK", "PD_EINVAL", "PD_ERANGE", "PD_ENOMEM", "PD_EDEVICE", "PD_ENOCONV"]):
+        assert L.pd_status_str(s).decode() == name
+
+
+def test_dimension_and_sizes():
+    L = pdg.load()
+    for om in range(1, 63):
+        for n in (0, 1, om // 3, om // 2, om):
+            assert pdg.dimension(om, n) == math.comb(om, n)
+    assert pdg.dimension(0, 0) == 0 and pdg.dimension(63, 2) == 0 and pdg.dimension(10, 11) == 0
+    assert L.pd_basis_bytes(10, 11, 1) == 0
+    b0 = L.pd_basis_bytes(28, 14, 0)
+    b1 = L.pd_basis_bytes(28, 14, 1)
+    assert b0 > 0 and b1 - b0 >= 8 * 40116600 and b1 % 256 == 0
+
+
+def test_basis_create_rejects_bad_space_before_device_work():
+    L = pdg.load()
+    h = ctypes.c_void_p()
+    assert L.pd_basis_create(70, 3, 0, None, 0, None, ctypes.byref(h)) == pdg.PD_EINVAL
+    assert L.pd_basis_create(10, 4, 1, None, 10, None, ctypes.byref(h)) == pdg.PD_ENOMEM
+    assert b"need" in L.pd_last_error()
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 20, 50, 64])
+def test_tridiag_lowest_against_library_eigh(m):
+    rng = np.random.default_rng(m)
+    a = rng.normal(size=m) * 3
+    b = rng.normal(size=max(m - 1, 0))
+    th, y = pdg.tridiag_lowest(a, b)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    w, Z = np.linalg.eigh(T)
+    assert abs(th - w[0]) <= 1e-13 * max(1.0, np.abs(w).max())
+    z = Z[:, 0] * (1 if Z[0, 0] >= 0 else -1)
+    assert np.allclose(y, z, atol=1e-10)
+    assert abs(np.linalg.norm(y) - 1) < 1e-14
+
+
+def test_tridiag_lowest_degenerate_offdiagonal():
+    a = np.array([3.0, 1.0, 2.0, 1.5])
+    b = np.array([0.0, 0.0, 0.0])
+    th, y = pdg.tridiag_lowest(a, b)
+    assert th == pytest.approx(1.0, abs=1e-14)
+    assert abs(abs(y[1]) - 1.0) < 1e-12
+
+
+def test_splitmix64_published_value():
+    # SplitMix64 from state 0: the first output is 0xE220A8397B1DCDAF
+    assert int(inputs.splitmix64(0, 0, 1)[0]) == 0xE220A8397B1DCDAF
+    u = inputs.uniform01(123, 0, 100000)
+    assert 0 <= u.min() and u.max() < 1 and abs(u.mean() - 0.5) < 0.01
+
+
+def test_instance_recipes_shapes_and_signs():
+    om, n, eps, V = inputs.c1_instance(0)
+    assert (om, n) == (16, 8) and np.all(np.diff(eps) >= 0) and eps.max() < 10
+    assert np.array_equal(V, V.T) and np.all(V < 0) and np.all(-V <= 0.3 * 1.2 + 1e-15)
+    for seed in range(50):
+        om, n, eps, V = inputs.family3_instance(seed)
+        assert 10 <= om <= 24 and math.ceil(om / 4) <= n <= om // 2
+        assert np.array_equal(V, V.T) and np.all(V < 0)

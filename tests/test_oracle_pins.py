@@ -179,6 +179,21 @@ def test_sigma_equals_dense_matvec_and_hash_path(oracle_mod):
     assert np.array_equal(y3, y1[rows])
     y4 = oracle_mod.sigma(omega, n, eps, V, b, x, "hash", rows=(5, 50))
     assert np.array_equal(y4, y1[5:50])
+    y5 = oracle_mod.sigma_block(omega, n, eps, V, x, 3, b.size)
+    assert np.array_equal(y5, y1[3:])
+
+
+def test_row_terms_reproduce_dense_rows(oracle_mod):
+    omega, n = 11, 4
+    eps, V = _rand_inst(omega, 17)
+    H = oracle_mod.dense_h(omega, n, eps, V)
+    rows = np.array([0, 3, 100, 329])
+    diag, tg, cf = oracle_mod.row_terms(omega, n, eps, V, rows)
+    for q, r in enumerate(rows):
+        row = np.zeros(H.shape[0])
+        row[r] += diag[q]
+        np.add.at(row, tg[q], cf[q])
+        assert np.array_equal(row, H[r])
 
 
 def test_sigma_dyadic_exact(oracle_mod):
