@@ -1,0 +1,198 @@
+// Matrix-free y = H x over the seniority-zero basis (Sec. 3.3).
+//
+// Row k of H has the diagonal of Eq. diagonal and one element V_EO for every
+// pair hop |j> = S+_E S-_O |k> (occupied O, empty E), n(omega-n) of them.  The
+// paper regenerates these elements on the fly and finds j with the hash of
+// Sec. 3.2; here one lane owns one row and finds j without any search:
+//
+//   * the lane recovers its state from the rank k (greedy inverse of the
+//     hash) so no basis array is read;
+//   * with occupied positions p_1 < ... < p_n, rank = sum_j C(p_j, j).  A hop
+//     a = p_r -> b shifts the indices of the occupied orbits between a and b
+//     by one, so the target rank is rank + A(a) + B(b), where A depends only
+//     on the removed orbit and B only on the added one (the "up" pair of terms
+//     when b > a, the "down" pair when b < a).  Both are differences of suffix
+//     sums of binomials over the occupied orbits above a (resp. b):
+//         up:   A = S_m(a) - S_0(a) - C(a, r),      B = S_0(b) - S_m(b) + C(b, t)
+//         down: A = S_0(a) - S_p(a) - C(a, r+1),    B = S_p(b) - S_0(b) + C(b, t+1)
+//     with S_c(q) = sum over occupied p_j > q of C(p_j, j + c) (c = 0, -1, +1)
+//     and t = number of occupied orbits below b;
+//   * rank + A for every occupied orbit sits in registers (the pair count NN
+//     is a template parameter, so the loops unroll completely); the lane then
+//     walks the orbits from the top, updating the suffix sums, and at every
+//     empty orbit b computes all NN targets, issues all NN gathers, then
+//     accumulates -- NN loads in flight per lane.
+//
+// Lanes of a wave hold consecutive ranks, which share their high orbits.
+// Walking and numbering orbits from the top makes every lane do the same
+// physical hop at the same time on those shared orbits, so those gathers hit
+// consecutive addresses.
+//
+// When n > omega - n the kernel works in the complementary space (holes as
+// particles, COMP): the state ~s of rank dim-1-k has omega-n pairs, a hop O->E
+// of s is the hop E->O of ~s, and V is symmetric, so the same code applies
+// with ranks mirrored.  NN = min(n, omega-n) <= 20: a larger value would mean
+// dim >= C(42, 21) ~ 5e11, beyond any GPU memory.
+//
+// Rank arithmetic is modular in R (uint32 whenever dim < 2^32): every target
+// lies in [0, dim), so wrap-around in intermediate sums cancels.
+#pragma once
+
+#include "pd_internal.h"
+
+namespace pd {
+namespace sigma_detail {
+
+constexpr int kThreads = 256;
+constexpr int64_t kMaxGrid = 256 * 16;
+
+template <typename R, typename T>
+struct Params {
+    int omega;
+    int nn;        // pairs in the working space (n, or omega - n when mirrored)
+    int ks;        // binomial table row stride (nn + 2)
+    int64_t dim;
+    int64_t ntiles;
+    const T *__restrict__ x;
+    T *__restrict__ y;
+    const T *__restrict__ d;   // omega pair energies
+    const T *__restrict__ V;   // omega x omega
+    T dsum;                    // sum of d (for the mirrored diagonal)
+};
+
+template <typename R, typename T, int NN, bool COMP>
+__global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int omega = P.omega, ks = P.ks;
+    R *Ct = reinterpret_cast<R *>(smem);
+    const int ct_elems = omega * ks;
+    T *Vs = reinterpret_cast<T *>(smem + ((ct_elems * (int)sizeof(R) + 15) & ~15));
+    T *ds = Vs + omega * omega;
+
+    for (int i = threadIdx.x; i < ct_elems; i += kThreads) {
+        int p = i / ks, k = i - p * ks;
+        Ct[i] = (R)g_binom.v[p][k];
+    }
+    for (int i = threadIdx.x; i < omega * omega; i += kThreads) Vs[i] = P.V[i];
+    for (int i = threadIdx.x; i < omega; i += kThreads) ds[i] = P.d[i];
+    __syncthreads();
+
+    const int64_t dim = P.dim;
+    const T *__restrict__ x = P.x;
+    for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
+        const int64_t row = tile * kThreads + threadIdx.x;
+        if (row >= dim) continue;
+        const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
+
+        // state of rank rk: greedy, orbits from the top
+        uint64_t s = 0;
+        {
+            R rem = rk;
+            int k = NN;
+            for (int p = omega - 1; p >= 0; --p) {
+                R c = Ct[p * ks + k];
+                if (k > 0 && c <= rem) {
+                    s |= 1ull << p;
+                    rem -= c;
+                    --k;
+                }
+            }
+        }
+
+        // rank + removed-orbit terms, occupied orbits numbered from the top
+        R rup[NN > 0 ? NN : 1], rdn[NN > 0 ? NN : 1];
+        int apos[NN > 0 ? NN : 1];
+        T dacc = T(0);
+        {
+            uint64_t occ = s;
+            R s0 = 0, sm = 0, sp = 0;
+#pragma unroll
+            for (int r = 0; r < NN; ++r) {
+                const int a = 63 - __clzll((long long)occ);
+                occ &= ~(1ull << a);
+                const int j = NN - r;
+                const R c0 = Ct[a * ks + j], cm = Ct[a * ks + j - 1], cp = Ct[a * ks + j + 1];
+                rup[r] = rk + (sm - s0 - c0);
+                rdn[r] = rk + (s0 - sp - cp);
+                apos[r] = a;
+                s0 += c0;
+                sm += cm;
+                sp += cp;
+                dacc += ds[a];
+            }
+        }
+
+        T acc = (COMP ? (P.dsum - dacc) : dacc) * x[row];
+        R s0 = 0, sm = 0, sp = 0;
+        int above = 0;
+        for (int p = omega - 1; p >= 0; --p) {
+            if ((s >> p) & 1ull) {
+                const int j = NN - above;
+                s0 += Ct[p * ks + j];
+                sm += Ct[p * ks + j - 1];
+                sp += Ct[p * ks + j + 1];
+                ++above;
+            } else if (NN > 0) {
+                const int t = NN - above;
+                const R bup = s0 - sm + Ct[p * ks + t];
+                const R bdn = sp - s0 + Ct[p * ks + t + 1];
+                const T *Vrow = Vs + p * omega;
+                T xv[NN > 0 ? NN : 1];
+#pragma unroll
+                for (int r = 0; r < NN; ++r) {
+                    const R jt = (p > apos[r]) ? (R)(rup[r] + bup) : (R)(rdn[r] + bdn);
+                    const int64_t jx = COMP ? (dim - 1 - (int64_t)jt) : (int64_t)jt;
+                    xv[r] = x[jx];
+                }
+#pragma unroll
+                for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
+            }
+        }
+        P.y[row] = acc;
+    }
+}
+
+template <typename R, typename T, int NN, bool COMP>
+hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
+    size_t ct_bytes = ((size_t)P.omega * P.ks * sizeof(R) + 15) & ~size_t(15);
+    size_t smem = ct_bytes + ((size_t)P.omega * P.omega + P.omega) * sizeof(T);
+    int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
+    hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP>), dim3((unsigned)grid), dim3(kThreads), smem, stream, P);
+    return hipGetLastError();
+}
+
+template <typename R, typename T, bool COMP>
+hipError_t dispatch_nn(const Params<R, T> &P, hipStream_t stream) {
+    switch (P.nn) {
+#define PD_NN_CASE(K) \
+    case K: return launch_nn<R, T, K, COMP>(P, stream);
+        PD_NN_CASE(0) PD_NN_CASE(1) PD_NN_CASE(2) PD_NN_CASE(3) PD_NN_CASE(4) PD_NN_CASE(5) PD_NN_CASE(6)
+        PD_NN_CASE(7) PD_NN_CASE(8) PD_NN_CASE(9) PD_NN_CASE(10) PD_NN_CASE(11) PD_NN_CASE(12) PD_NN_CASE(13)
+        PD_NN_CASE(14) PD_NN_CASE(15) PD_NN_CASE(16) PD_NN_CASE(17) PD_NN_CASE(18) PD_NN_CASE(19)
+        PD_NN_CASE(20)
+#undef PD_NN_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// y = H x with rank type R and value type T.
+template <typename R, typename T>
+hipError_t launch_typed(int omega, int n, int64_t dim, const T *d, const T *V, T dsum, const T *x, T *y,
+                        hipStream_t stream) {
+    Params<R, T> P;
+    const bool comp = n > omega - n;
+    P.omega = omega;
+    P.nn = comp ? omega - n : n;
+    P.ks = P.nn + 2;
+    P.dim = dim;
+    P.ntiles = (dim + kThreads - 1) / kThreads;
+    P.x = x;
+    P.y = y;
+    P.d = d;
+    P.V = V;
+    P.dsum = dsum;
+    return comp ? dispatch_nn<R, T, true>(P, stream) : dispatch_nn<R, T, false>(P, stream);
+}
+
+}  // namespace sigma_detail
+}  // namespace pd
