@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size in rows (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=5)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="for counter runs: one 1 GiB device copy (the known-size reference), then "
+                         "--sigma-reps FP32 and FP64 products of the workload, and exit")
     return ap.parse_args()
 
 
@@ -47,10 +50,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_from_profiles(kernel_tag, workload_tag):
-    """Per-launch HBM bytes of a kernel from a committed rocprofv3 counter summary
-    (profiles/<kernel>_<workload>_counters.txt, lines 'key: value'), or None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_{workload_tag}_counters.txt")
+KERNEL_SOURCES = ["paper_2001_01978_amd/csrc/sigma_impl.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(name):
+    """Per-launch HBM bytes of the dominant kernel from the committed rocprofv3
+    counter summary profiles/<name>.txt ('key: value' lines), or None when the
+    summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", name + ".txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -58,6 +74,8 @@ def traffic_from_profiles(kernel_tag, workload_tag):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -107,6 +125,22 @@ def main():
     basis = pairdiag.Basis(om, n, store_states=False)
     D = basis.dim
     log(f"workload omega={om} n={n} dim={D} hops/row={K}")
+
+    if args.kernel_only:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").uniform_(-1, 1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)                       # reads and writes exactly 1 GiB each
+        torch.cuda.synchronize()
+        del src, dst
+        for dt in (torch.float32, torch.float64):
+            x = torch.empty(D, dtype=dt, device="cuda").uniform_(-1, 1)
+            y = torch.empty_like(x)
+            for _ in range(args.sigma_reps):
+                basis.sigma(eps, V, x, y)
+            torch.cuda.synchronize()
+            del x, y
+        log(f"kernel-only run done (kernel source {kernel_source_hash()})")
+        return
 
     # ---- per-product sigma rates (separate buffers, same stream)
     sig = {}
@@ -170,7 +204,7 @@ def main():
         cpu = cpu_baseline(om, n, eps, V, args.cpu_rows)
         log(f"cpu baseline: {cpu['value']:.3e} nnz/s on {cpu['cores']} threads")
 
-    traffic = traffic_from_profiles("sigma_f32", f"omega{om}_n{n}")
+    traffic = traffic_from_profiles(f"sigma_f32_omega{om}_n{n}_counters")
     out = {
         "metric": "sigma nonzeros/s + HBM GB/s; time-to-E0 at Omega=32,n=16, plain vs mixed vs warm",
         "value": value,

@@ -79,7 +79,19 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
 
     const int64_t dim = P.dim;
     const T *__restrict__ x = P.x;
-    for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
+    // Workgroups are dealt to the 8 XCDs round-robin (workgroup id mod 8).
+    // Each XCD walks its own contiguous eighth of the tiles, so the rows in
+    // flight on one XCD, and the x lines their hops touch, stay together in
+    // that XCD's L2 instead of being spread over all eight.
+    int64_t t_begin = blockIdx.x, t_end = P.ntiles, t_step = gridDim.x;
+    if ((gridDim.x & 7) == 0 && P.ntiles >= (int64_t)gridDim.x) {
+        const int64_t per_xcd = (P.ntiles + 7) / 8;
+        const int64_t xcd = blockIdx.x & 7;
+        t_begin = xcd * per_xcd + (blockIdx.x >> 3);
+        t_end = (xcd + 1) * per_xcd < P.ntiles ? (xcd + 1) * per_xcd : P.ntiles;
+        t_step = gridDim.x >> 3;
+    }
+    for (int64_t tile = t_begin; tile < t_end; tile += t_step) {
         const int64_t row = tile * kThreads + threadIdx.x;
         if (row >= dim) continue;
         const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
@@ -157,6 +169,7 @@ hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
     size_t ct_bytes = ((size_t)P.omega * P.ks * sizeof(R) + 15) & ~size_t(15);
     size_t smem = ct_bytes + ((size_t)P.omega * P.omega + P.omega) * sizeof(T);
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
+    if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
     hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP>), dim3((unsigned)grid), dim3(kThreads), smem, stream, P);
     return hipGetLastError();
 }
