@@ -164,6 +164,50 @@ size_t pd_occupations_workspace_bytes(pd_basis b);
 pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size_t work_bytes,
                          double *occ_host, hipStream_t stream);
 
+/* ------------------------------------------------------------------ batched
+ * Many independent ground-state problems (as in a mean-field sweep that
+ * replaces BCS by the exact solution, Sec. 1 and Sec. 6) solved in ONE
+ * persistent kernel launch captured in a HIP graph: a device work queue hands
+ * instances, largest first, to workgroups, and each workgroup runs the whole
+ * restarted Lanczos iteration of pd_lanczos_ground for its instance (FP64,
+ * random start with seed o->seed + instance index, tol / max_restarts / krylov
+ * from o; krylov <= 32).  Limits per instance: omega <= 32, min(n, omega-n) <= 12
+ * (instances with n > omega - n are solved as their particle-hole complement,
+ * an exact identity: E0 = E0' + sum_i (2 eps_i + V_ii), <N_i> = 2 - <N_i>').
+ * Inputs (host): omega[count], n[count]; eps_packed: the omega_i pair energies
+ * of each instance back to back; V_packed: the omega_i x omega_i row-major
+ * couplings back to back.  Outputs (host): E0_out[count]; occ_out (optional):
+ * sum(omega_i) doubles, packed like eps; info_out (optional, per instance:
+ * iterations, restarts, converged, residual); binfo (optional).
+ * block: workgroup size 128, 256 or 512, or 0 to autotune it on a sample of the
+ * batch (the choice is cached per batch shape for the life of the process).
+ * Instances whose cost exceeds half the mean load of one workgroup are first
+ * solved by teams of workgroups (8 teams of grid/8) that split the rows and
+ * meet at a bounded-wait barrier; if a wait times out (another kernel holding
+ * compute units) the call returns PD_EDEVICE.  The workspace holds one Krylov
+ * slot per workgroup sized for the largest instance.  Returns PD_ENOCONV if any instance missed the tolerance (all
+ * outputs filled).  info_out[i].seconds is the device time the instance took.
+ * Synchronises `stream`. */
+typedef struct {
+    int block;             /* workgroup size used */
+    int grid;              /* persistent workgroups (one per compute unit, at most count) */
+    int tuned;             /* 1 if this call ran the autotuner */
+    int teams;             /* workgroup teams for the large instances (0: none) */
+    int team_size;         /* workgroups per team */
+    int large;             /* instances solved by teams */
+    int converged;         /* instances that met the tolerance */
+    long long total_iterations;
+    double tune_seconds;
+    double kernel_seconds; /* the graph launch, to completion */
+    double seconds;        /* the whole call */
+} pd_batch_info;
+
+size_t pd_batched_workspace_bytes(int count, const int *omega, const int *n, const pd_lanczos_opts *o);
+pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, const double *eps_packed,
+                                    const double *V_packed, const pd_lanczos_opts *o, int block,
+                                    void *work_dev, size_t work_bytes, double *E0_out, double *occ_out,
+                                    pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream);
+
 /* ------------------------------------------------------------------ host utility
  * Lowest eigenpair of the m x m symmetric tridiagonal matrix with diagonal
  * alpha[0..m) and off-diagonal beta[0..m-1) (the Lanczos matrix L of

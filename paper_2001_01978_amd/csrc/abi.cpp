@@ -325,6 +325,28 @@ pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size
     return PD_OK;
 }
 
+size_t pd_batched_workspace_bytes(int count, const int *omega, const int *n, const pd_lanczos_opts *o) {
+    if (check_opts(o) != PD_OK || batched_validate(count, omega, n, o) != PD_OK) return 0;
+    return batched_workspace_bytes(count, omega, n, o);
+}
+
+pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, const double *eps_packed,
+                                    const double *V_packed, const pd_lanczos_opts *o, int block, void *work_dev,
+                                    size_t work_bytes, double *E0_out, double *occ_out, pd_lanczos_info *info_out,
+                                    pd_batch_info *binfo, hipStream_t stream) {
+    pd_status st = check_opts(o);
+    if (st != PD_OK) return st;
+    if ((st = batched_validate(count, omega, n, o)) != PD_OK) return st;
+    if (!eps_packed || !V_packed || !E0_out) return fail(PD_EINVAL, "eps_packed, V_packed and E0_out are required");
+    if (block != 0 && block != 128 && block != 256 && block != 512) return fail(PD_EINVAL, "block=%d", block);
+    size_t need = batched_workspace_bytes(count, omega, n, o);
+    if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+    if ((st = check_device_ptr(work_dev, "work_dev", need)) != PD_OK) return st;
+    if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
+    return batched_run(count, omega, n, eps_packed, V_packed, o, block, work_dev, work_bytes, E0_out, occ_out,
+                       info_out, binfo, stream);
+}
+
 int pd_tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y) {
     if (!alpha || !theta || !y || (m > 1 && !beta)) return -1;
     return tridiag_lowest(m, alpha, beta, theta, y);

@@ -1,0 +1,776 @@
+// Many independent ground-state problems in one persistent launch.
+//
+// Each workgroup takes the next instance from a device work queue (one
+// atomic counter over instances sorted largest-first by the host, i.e. the
+// longest-processing-time order) and runs the whole restarted Lanczos
+// iteration of Sec. 3.4 for it: the product (the same per-row hop code as
+// the single-instance sigma), Gram-Schmidt against all stored vectors
+// applied twice, the tridiagonal eigensolver (bisection + inverse
+// iteration, one lane), the restart, the convergence test of Eq. convergence
+// and the occupation numbers -- all without returning to the host.  The
+// Krylov vectors of an instance live in a per-workgroup slot of the caller's
+// workspace and stay in L2 / the Infinity Cache for all but the largest
+// instances.  The queue reset and the solver launch are captured into one
+// HIP graph.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "pd_internal.h"
+#include "sigma_impl.h"
+#include "tridiag.h"
+
+namespace pd {
+namespace batched {
+
+constexpr int kMaxPairs = 12;    // min(n, omega - n) of a batched instance
+constexpr int kMaxOmegaB = 32;   // orbits of a batched instance
+constexpr int kMaxKrylovB = 32;  // Krylov vectors per cycle
+constexpr int kMaxWaves = 16;    // blocks of at most 1024 threads
+
+struct Instance {
+    int omega, n, nn, comp;
+    int64_t dim;
+    int64_t coef;     // offset (doubles) of d[omega] then V[omega*omega] in the coefficient array
+    int64_t occ_off;  // offset (doubles) of this instance's occupations in the output
+    uint64_t seed;
+    int orig;         // index in the caller's order
+    int m;            // Krylov vectors per cycle: min(krylov, dim)
+    double dsum;      // sum of the pair energies
+    double dscale;    // max |pair energy| (denominator guard of the residual)
+    double eshift;    // energy of the original problem = eigenvalue here + eshift
+};
+
+struct Result {
+    double E0, residual;
+    int iterations, restarts, converged, pad;
+    long long ticks;  // wall_clock64() ticks spent on the instance
+};
+
+struct Args {
+    const Instance *inst;
+    int count;
+    int n_large;          // instances [0, n_large) of the sorted table are solved by teams
+    int teams;            // 0, or number of teams (the grid is teams * team_size workgroups)
+    int team_size;
+    int *counter;         // small-instance queue (starts at n_large)
+    int *large_counter;   // large-instance queue
+    int *team_ctl;        // per team: barrier count, generation, mailbox (each on its own 128-byte line)
+    double *team_part;    // per team: 2 buffers x 8 values x team_size partial sums
+    int *error;           // set when a team barrier times out
+    long long spin_limit;
+    const double *coef;
+    double *slots;
+    int64_t slot_doubles;
+    double tol;
+    int max_restarts;
+    Result *res;
+    double *occ;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+struct Shared {
+    uint32_t Ct[kMaxOmegaB * (kMaxPairs + 2)];
+    double Vs[kMaxOmegaB * kMaxOmegaB];
+    double ds[kMaxOmegaB];
+    double scratch[kMaxWaves * 8];
+    double alpha[kMaxKrylovB], beta[kMaxKrylovB], y[kMaxKrylovB];
+    double c[kMaxKrylovB + 8], red[8];
+    double A[kMaxKrylovB * kMaxKrylovB], v[kMaxKrylovB];
+    double theta;
+    int idx, flag, abort;
+};
+
+// The workgroups that solve one instance together (size 1 for small ones).
+struct Team {
+    int G, g;             // team size, member index
+    int64_t r0, r1;       // rows owned by this member
+    int *ctl;             // barrier count at ctl[0], generation at ctl[32], mailbox at ctl[64]
+    double *part;         // 2 x 8 x G partial sums
+    int parity;
+};
+
+constexpr int kCtlInts = 96;
+
+// Barrier over the team's workgroups.  Thread 0 of each member arrives on a
+// device-scope counter; the last one resets it and bumps the generation the
+// others spin on.  The spin is bounded: on timeout the error flag is raised
+// and every member abandons the instance, so the kernel always drains.
+__device__ bool team_sync(const Args &A, Team &T, Shared &sh) {
+    __syncthreads();
+    if (T.G == 1) return true;
+    if (threadIdx.x == 0) {
+        int *count = T.ctl, *gen = T.ctl + 32;
+        __threadfence();
+        const int g0 = atomicAdd(gen, 0);
+        int ok = 1;
+        if (atomicAdd(count, 1) == T.G - 1) {
+            atomicExch(count, 0);
+            __threadfence();
+            atomicAdd(gen, 1);
+        } else {
+            long long spins = 0;
+            while (atomicAdd(gen, 0) == g0) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > A.spin_limit || atomicAdd(A.error, 0) != 0) {
+                    atomicExch(A.error, 1);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        sh.abort = ok ? 0 : 1;
+    }
+    __syncthreads();
+    return sh.abort == 0;
+}
+
+// Sum NV per-thread values over the team; totals land in out[0..NV) of every member.
+template <int NV>
+__device__ __forceinline__ bool team_sum(const Args &A, Team &T, double (&v)[NV], Shared &sh, double *out) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double t = wave_sum(v[j]);
+        if (lane == 0) sh.scratch[wid * NV + j] = t;
+    }
+    __syncthreads();
+    double s = 0.0;
+    if ((int)threadIdx.x < NV) {
+        for (int w = 0; w < nw; ++w) s += sh.scratch[w * NV + threadIdx.x];
+        if (T.G == 1) out[threadIdx.x] = s;
+        else T.part[(T.parity * 8 + threadIdx.x) * T.G + T.g] = s;
+    }
+    if (T.G == 1) {
+        __syncthreads();
+        return true;
+    }
+    if (!team_sync(A, T, sh)) return false;
+    if ((int)threadIdx.x < NV) {
+        const double *src = T.part + (T.parity * 8 + threadIdx.x) * T.G;
+        double t = 0.0;
+        for (int q = 0; q < T.G; ++q) t += src[q];
+        out[threadIdx.x] = t;
+    }
+    T.parity ^= 1;
+    __syncthreads();
+    return true;
+}
+
+template <int NN, bool COMP>
+__device__ void wg_sigma_nn(const Instance &I, const Team &T, const Shared &sh, const double *x, double *y) {
+    const int ks = I.nn + 2;
+    for (int64_t row = T.r0 + threadIdx.x; row < T.r1; row += blockDim.x)
+        y[row] = sigma_detail::sigma_row<uint32_t, double, NN, COMP>(row, I.dim, I.omega, ks, sh.Ct, sh.Vs, sh.ds,
+                                                                     I.dsum, x);
+}
+
+// Instances arrive with n <= omega - n (the host maps the others to their
+// particle-hole complement), so only the unmirrored kernels are needed.
+__device__ void wg_sigma(const Instance &I, const Team &T, const Shared &sh, const double *x, double *y) {
+    switch (I.nn) {
+#define PD_B_CASE(K) \
+    case K: wg_sigma_nn<K, false>(I, T, sh, x, y); break;
+        PD_B_CASE(0) PD_B_CASE(1) PD_B_CASE(2) PD_B_CASE(3) PD_B_CASE(4) PD_B_CASE(5) PD_B_CASE(6) PD_B_CASE(7)
+        PD_B_CASE(8) PD_B_CASE(9) PD_B_CASE(10) PD_B_CASE(11) PD_B_CASE(12)
+#undef PD_B_CASE
+        default: break;
+    }
+}
+
+// c[j] = Q[j] . p for j < nc (c in LDS).
+__device__ bool wg_gemvt(const Args &A, Team &T, const double *Q, int64_t ld, int nc, const double *p, Shared &sh) {
+    for (int j0 = 0; j0 < nc; j0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
+        for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
+            const double pi = p[i];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                if (j0 + jj < nc) acc[jj] += Q[(int64_t)(j0 + jj) * ld + i] * pi;
+        }
+        if (!team_sum<8>(A, T, acc, sh, sh.c + j0)) return false;
+    }
+    return true;
+}
+
+// p -= sum_j c[j] Q[j] (j < nc); ||p||^2 to sh.red[0].
+__device__ bool wg_update(const Args &A, Team &T, const double *Q, int64_t ld, int nc, double *p, Shared &sh) {
+    double acc[1] = {0.0};
+    for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
+        double v = p[i];
+        for (int j = 0; j < nc; ++j) v -= Q[(int64_t)j * ld + i] * sh.c[j];
+        p[i] = v;
+        acc[0] += v * v;
+    }
+    return team_sum<1>(A, T, acc, sh, sh.red);
+}
+
+// out = a * in over the member's rows, then a team barrier (out is read whole next).
+__device__ bool wg_scale(const Args &A, Team &T, const double *in, double a, double *out, Shared &sh) {
+    for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) out[i] = a * in[i];
+    return team_sync(A, T, sh);
+}
+
+__device__ void solve_instance(const Args &A, const Instance &I, double *slot, Team T, Shared &sh) {
+    const long long t_start = wall_clock64();
+    const int omega = I.omega, ks = I.nn + 2;
+    // stage tables (a barrier precedes any use)
+    for (int i = threadIdx.x; i < omega * ks; i += blockDim.x) {
+        int p = i / ks, k = i - p * ks;
+        sh.Ct[i] = (uint32_t)g_binom.v[p][k];
+    }
+    const double *d = A.coef + I.coef;
+    const double *V = d + kMaxOmegaB;
+    for (int i = threadIdx.x; i < omega * omega; i += blockDim.x) sh.Vs[i] = V[i];
+    for (int i = threadIdx.x; i < omega; i += blockDim.x) sh.ds[i] = d[i];
+
+    const int64_t dim = I.dim;
+    const int64_t ld = (dim + 63) & ~int64_t(63);
+    {
+        const int64_t chunk = ((dim + T.G - 1) / T.G + 63) & ~int64_t(63);
+        T.r0 = (int64_t)T.g * chunk < dim ? (int64_t)T.g * chunk : dim;
+        T.r1 = T.r0 + chunk < dim ? T.r0 + chunk : dim;
+    }
+    const int m = I.m;
+    double *Q = slot;
+    double *p = Q + (int64_t)m * ld;
+    double *w = p + ld;
+
+    int iterations = 0, cycle = 0;
+    bool converged = false, final_check = false, ok = true;
+    double residual = INFINITY, e0 = 0.0;
+
+    // start: x_k = 2 u_k - 1 with u_k from SplitMix64 (seed, k)
+    {
+        double acc[1] = {0.0};
+        for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
+            uint64_t z = I.seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z = z ^ (z >> 31);
+            double v = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+            w[i] = v;
+            acc[0] += v * v;
+        }
+        ok = team_sum<1>(A, T, acc, sh, sh.red) && wg_scale(A, T, w, 1.0 / sqrt(sh.red[0]), Q, sh);
+    }
+
+    for (cycle = 0; ok; ++cycle) {
+        int m_eff = m;
+        for (int k = 0; k < m; ++k) {
+            const double *qk = Q + (int64_t)k * ld;
+            wg_sigma(I, T, sh, qk, p);
+            __syncthreads();
+            ++iterations;
+            if (!(ok = wg_gemvt(A, T, Q, ld, k + 1, p, sh))) break;
+            const double alpha = sh.c[k];
+            if (!(ok = wg_update(A, T, Q, ld, k + 1, p, sh))) break;
+            if (!(ok = wg_gemvt(A, T, Q, ld, k + 1, p, sh))) break;
+            if (!(ok = wg_update(A, T, Q, ld, k + 1, p, sh))) break;
+            const double beta = sqrt(fmax(sh.red[0], 0.0));
+            if (threadIdx.x == 0) {
+                sh.alpha[k] = alpha;
+                sh.beta[k] = beta;
+            }
+            if (k == 0) {
+                e0 = alpha + I.eshift;
+                residual = beta / fmax(fabs(e0), 1e-3 * I.dscale);
+                if (residual <= A.tol) converged = true;
+                if (converged || final_check) break;
+            }
+            double tnorm = 0.0;
+            __syncthreads();
+            for (int i = 0; i <= k; ++i) tnorm = fmax(tnorm, fabs(sh.alpha[i]) + sh.beta[i]);
+            if (beta <= 1e-14 * fmax(tnorm, 1e-300)) {
+                m_eff = k + 1;
+                break;
+            }
+            if (k + 1 < m && !(ok = wg_scale(A, T, p, 1.0 / beta, Q + (int64_t)(k + 1) * ld, sh))) break;
+        }
+        if (!ok || converged || final_check) break;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            sh.flag = tridiag_lowest_work(m_eff, sh.alpha, sh.beta, &sh.theta, sh.y, sh.A, sh.v);
+        __syncthreads();
+        if (sh.flag != 0) break;
+        // psi = Q y, normalised, becomes q_1
+        {
+            double acc[1] = {0.0};
+            for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
+                double v = 0.0;
+                for (int j = 0; j < m_eff; ++j) v += Q[(int64_t)j * ld + i] * sh.y[j];
+                w[i] = v;
+                acc[0] += v * v;
+            }
+            ok = team_sum<1>(A, T, acc, sh, sh.red) && wg_scale(A, T, w, 1.0 / sqrt(sh.red[0]), Q, sh);
+        }
+        if (cycle >= A.max_restarts) final_check = true;
+    }
+
+    // occupations of q_1: <N_i> = 2 sum_k q_k^2 [orbit i occupied]
+    for (int i0 = 0; ok && i0 < omega; i0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
+        for (int64_t r = T.r0 + threadIdx.x; r < T.r1; r += blockDim.x) {
+            uint64_t s = 0, rem = (uint64_t)r;
+            int kk = I.n;
+            for (int q = omega - 1; q >= 0; --q) {
+                uint64_t c = g_binom.v[q][kk];
+                if (kk > 0 && c <= rem) {
+                    s |= 1ull << q;
+                    rem -= c;
+                    --kk;
+                }
+            }
+            const double wq = Q[r] * Q[r];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) acc[jj] += ((s >> (i0 + jj)) & 1ull) ? wq : 0.0;
+        }
+        if (!(ok = team_sum<8>(A, T, acc, sh, sh.red))) break;
+        if (T.g == 0 && (int)threadIdx.x < 8 && i0 + (int)threadIdx.x < omega)
+            A.occ[I.occ_off + i0 + threadIdx.x] = 2.0 * sh.red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && T.g == 0) {
+        Result r;
+        r.E0 = e0;
+        r.residual = residual;
+        r.iterations = iterations;
+        r.restarts = cycle;
+        r.converged = (ok && converged) ? 1 : 0;
+        r.pad = ok ? 0 : 1;
+        r.ticks = wall_clock64() - t_start;
+        A.res[I.orig] = r;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void batched_kernel(Args A) {
+    __shared__ Shared sh;
+    // Phase 1 (teams > 0): large instances, one team of workgroups each
+    // (team = workgroup id mod teams, member = id / teams, all members work in
+    // the slot of member 0).  Phase 2: the rest, one workgroup each.  A single
+    // call site of solve_instance keeps one copy of the solver in the kernel.
+    Team T;
+    int phase = A.teams > 0 ? 1 : 2;
+    const int t = A.teams > 0 ? (int)(blockIdx.x % A.teams) : 0;
+    for (;;) {
+        int idx;
+        double *slot;
+        if (phase == 1) {
+            T.G = A.team_size;
+            T.g = blockIdx.x / A.teams;
+            T.ctl = A.team_ctl + t * kCtlInts;
+            T.part = A.team_part + (int64_t)t * 16 * A.team_size;
+            T.parity = 0;
+            if (T.g == 0 && threadIdx.x == 0) atomicExch(T.ctl + 64, atomicAdd(A.large_counter, 1));
+            if (!team_sync(A, T, sh)) break;
+            if (threadIdx.x == 0) sh.idx = atomicAdd(T.ctl + 64, 0);
+            __syncthreads();
+            // uniform across the workgroup: keep it (and the instance record) in scalar registers
+            idx = __builtin_amdgcn_readfirstlane(sh.idx);
+            // everyone has read the mailbox before member 0 may overwrite it
+            if (!team_sync(A, T, sh)) break;
+            if (idx >= A.n_large) {
+                phase = 2;
+                continue;
+            }
+            slot = A.slots + (int64_t)t * A.slot_doubles;
+        } else {
+            T.G = 1;
+            T.g = 0;
+            T.ctl = nullptr;
+            T.part = nullptr;
+            T.parity = 0;
+            if (threadIdx.x == 0) sh.idx = atomicAdd(A.counter, 1);
+            __syncthreads();
+            idx = __builtin_amdgcn_readfirstlane(sh.idx);
+            __syncthreads();
+            if (idx >= A.count) break;
+            slot = A.slots + (int64_t)blockIdx.x * A.slot_doubles;
+        }
+        solve_instance(A, A.inst[idx], slot, T, sh);
+        if (phase == 1) {
+            if (threadIdx.x == 0) sh.flag = atomicAdd(A.error, 0);
+            __syncthreads();
+            if (sh.flag != 0) break;
+        }
+    }
+}
+
+__global__ void reset_queue(int *counter, int start, int *large_counter, int *team_ctl, int nctl, int *error) {
+    for (int i = threadIdx.x; i < nctl; i += blockDim.x) team_ctl[i] = 0;
+    if (threadIdx.x == 0) {
+        *counter = start;
+        *large_counter = 0;
+        *error = 0;
+    }
+}
+
+}  // namespace batched
+}  // namespace pd
+
+// ------------------------------------------------------------------ host side
+namespace pd {
+namespace batched {
+namespace {
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+struct Layout {
+    size_t inst = 0, sample = 0, coef = 0, counter = 0, team_ctl = 0, team_part = 0, res = 0, occ = 0, slots = 0,
+           total = 0;
+    int64_t slot_doubles = 0, coef_doubles = 0, occ_doubles = 0;
+    int grid = 0, m_max = 0, nslots = 0;
+    int teams = 0, n_large = 0;
+};
+
+constexpr int kSample = 32;
+
+// Work of one restart cycle of instance i (products plus Gram-Schmidt).
+double instance_cost(int omega, int n, int krylov) {
+    const int nn = std::min(n, omega - n);
+    const double dim = (double)binom_host(omega, n);
+    const double m = std::min<double>(krylov, dim);
+    return dim * ((double)nn * (omega - nn) + 1.0 + 2.0 * m);
+}
+
+// Schedule: with a full grid (a multiple of 8 workgroups), 8 teams of grid/8
+// workgroups first solve the costliest instances (sorted order), then every
+// workgroup drains the rest alone.  The split is chosen on the cost model:
+// phase 1 takes (cost of the first s) / (grid * team efficiency), phase 2 the
+// larger of (cost of the rest) / grid and one remaining instance times 3
+// (iteration counts of equal-size instances differ by that much).
+void plan_schedule(int count, const int *omega, const int *n, int krylov, int grid, const std::vector<int> &order,
+                   int *teams, int *n_large) {
+    *teams = 0;
+    *n_large = 0;
+    if (grid < 64 || grid % 8 != 0) return;
+    std::vector<double> cost(count);
+    double total = 0.0;
+    for (int i = 0; i < count; ++i) total += (cost[i] = instance_cost(omega[i], n[i], krylov));
+    const double team_eff = 0.85;  // barriers and shorter rows per workgroup
+    double best = 1e300, done = 0.0;
+    for (int split = 0; split <= count; ++split) {
+        const double rest = total - done;
+        const double largest_rest = split < count ? cost[order[split]] : 0.0;
+        const double t = done / (grid * team_eff) + std::max(rest / grid, 3.0 * largest_rest);
+        if (t < best) {
+            best = t;
+            *n_large = split;
+        }
+        if (split < count) done += cost[order[split]];
+    }
+    if (*n_large > 0) *teams = 8;
+}
+
+std::vector<int> cost_order(int count, const int *omega, const int *n, int krylov) {
+    std::vector<double> cost(count);
+    for (int i = 0; i < count; ++i) cost[i] = instance_cost(omega[i], n[i], krylov);
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return order;
+}
+
+Layout layout_for(int count, const int *omega, const int *n, int krylov) {
+    Layout L;
+    int64_t dmax = 1;
+    for (int i = 0; i < count; ++i) {
+        dmax = std::max<int64_t>(dmax, (int64_t)binom_host(omega[i], n[i]));
+        L.coef_doubles += kMaxOmegaB + (int64_t)omega[i] * omega[i];
+        L.occ_doubles += omega[i];
+    }
+    L.m_max = (int)std::min<int64_t>(krylov, dmax);
+    const int64_t ld = (dmax + 63) & ~int64_t(63);
+    L.slot_doubles = ((int64_t)(L.m_max + 2) * ld + 31) & ~int64_t(31);
+    L.grid = std::min(count, device_cus());
+    plan_schedule(count, omega, n, krylov, L.grid, cost_order(count, omega, n, krylov), &L.teams, &L.n_large);
+    // every instance on teams: one Krylov slot per team; otherwise one per workgroup
+    L.nslots = (L.teams > 0 && L.n_large == count) ? L.teams : L.grid;
+    size_t off = 0;
+    L.inst = off;
+    off += align256(sizeof(Instance) * (size_t)count);
+    L.sample = off;
+    off += align256(sizeof(Instance) * kSample);
+    L.coef = off;
+    off += align256(sizeof(double) * (size_t)L.coef_doubles);
+    L.counter = off;    // small queue at +0, large queue at +64, error flag at +128
+    off += 256;
+    L.team_ctl = off;
+    off += align256(sizeof(int) * kCtlInts * 8);
+    L.team_part = off;
+    off += align256(sizeof(double) * 16 * (size_t)std::max(L.grid, 1));
+    L.res = off;
+    off += align256(sizeof(Result) * (size_t)count);
+    L.occ = off;
+    off += align256(sizeof(double) * (size_t)L.occ_doubles);
+    L.slots = off;
+    off += sizeof(double) * (size_t)L.slot_doubles * (size_t)L.nslots;
+    L.total = off;
+    return L;
+}
+
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int> g_tuned;
+
+}  // namespace
+}  // namespace batched
+
+size_t batched_workspace_bytes(int count, const int *omega, const int *n, const pd_lanczos_opts *o) {
+    return batched::layout_for(count, omega, n, o->krylov).total;
+}
+
+pd_status batched_validate(int count, const int *omega, const int *n, const pd_lanczos_opts *o) {
+    if (count < 1) return fail(PD_EINVAL, "count must be >= 1");
+    if (!omega || !n) return fail(PD_EINVAL, "omega and n must be host arrays");
+    if (o->krylov < 2 || o->krylov > batched::kMaxKrylovB)
+        return fail(PD_EINVAL, "batched krylov=%d outside [2, %d]", o->krylov, batched::kMaxKrylovB);
+    for (int i = 0; i < count; ++i) {
+        if (omega[i] < 1 || omega[i] > batched::kMaxOmegaB || n[i] < 0 || n[i] > omega[i])
+            return fail(PD_EINVAL, "instance %d: omega=%d n=%d outside [1, %d] x [0, omega]", i, omega[i], n[i],
+                        batched::kMaxOmegaB);
+        if (std::min(n[i], omega[i] - n[i]) > batched::kMaxPairs)
+            return fail(PD_ERANGE, "instance %d: min(n, omega-n) > %d", i, batched::kMaxPairs);
+    }
+    return PD_OK;
+}
+
+pd_status batched_run(int count, const int *omega, const int *n, const double *eps_packed, const double *V_packed,
+                      const pd_lanczos_opts *o, int block, void *work, size_t work_bytes, double *E0_out,
+                      double *occ_out, pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream) {
+    using namespace batched;
+    auto t0 = std::chrono::steady_clock::now();
+    Layout L = layout_for(count, omega, n, o->krylov);
+    if (work_bytes < L.total) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
+    unsigned char *base = static_cast<unsigned char *>(work);
+
+    // instances and coefficients (validated while packing)
+    std::vector<Instance> inst(count);
+    std::vector<char> flipped(count, 0);
+    std::vector<double> coef((size_t)L.coef_doubles, 0.0);
+    int64_t coff = 0, ooff = 0, eoff = 0, voff = 0;
+    CoefBlock blk;
+    for (int i = 0; i < count; ++i) {
+        pd_status st = pack_coefficients(omega[i], n[i], eps_packed + eoff, V_packed + voff, &blk);
+        if (st != PD_OK) return fail(st, "instance %d: %s", i, last_error());
+        Instance &I = inst[i];
+        // n > omega - n: solve the particle-hole complement (omega - n pairs,
+        // pair energies -d_i, same V): H = (sum d) 1 + P H' P^T, so E0 = E0' + sum d
+        // and <N_i> = 2 - <N_i>'.
+        const bool flip = n[i] > omega[i] - n[i];
+        flipped[i] = flip;
+        I.omega = omega[i];
+        I.n = flip ? omega[i] - n[i] : n[i];
+        I.comp = 0;
+        I.nn = I.n;
+        I.dim = (int64_t)binom_host(omega[i], n[i]);
+        I.eshift = flip ? blk.dsum64 : 0.0;
+        I.coef = coff;
+        I.occ_off = ooff;
+        I.seed = o->seed + (uint64_t)i;
+        I.orig = i;
+        I.m = (int)std::min<int64_t>(o->krylov, I.dim);
+        I.dsum = flip ? -blk.dsum64 : blk.dsum64;
+        double sc = 0.0;
+        for (int q = 0; q < omega[i]; ++q) {
+            coef[coff + q] = flip ? -blk.d64[q] : blk.d64[q];
+            sc = std::max(sc, std::fabs(blk.d64[q]));
+        }
+        I.dscale = sc > 0.0 ? sc : 1.0;
+        for (int q = 0; q < omega[i] * omega[i]; ++q) coef[coff + kMaxOmegaB + q] = blk.V64[q];
+        coff += kMaxOmegaB + (int64_t)omega[i] * omega[i];
+        ooff += omega[i];
+        eoff += omega[i];
+        voff += (int64_t)omega[i] * omega[i];
+    }
+    const std::vector<int> order = cost_order(count, omega, n, o->krylov);
+    std::vector<Instance> sorted(count);
+    for (int i = 0; i < count; ++i) sorted[i] = inst[order[i]];
+
+    Instance *d_inst = reinterpret_cast<Instance *>(base + L.inst);
+    Instance *d_sample = reinterpret_cast<Instance *>(base + L.sample);
+    double *d_coef = reinterpret_cast<double *>(base + L.coef);
+    int *d_counter = reinterpret_cast<int *>(base + L.counter);
+    int *d_large = reinterpret_cast<int *>(base + L.counter + 64);
+    int *d_error = reinterpret_cast<int *>(base + L.counter + 128);
+    int *d_team_ctl = reinterpret_cast<int *>(base + L.team_ctl);
+    double *d_team_part = reinterpret_cast<double *>(base + L.team_part);
+    Result *d_res = reinterpret_cast<Result *>(base + L.res);
+    double *d_occ = reinterpret_cast<double *>(base + L.occ);
+    double *d_slots = reinterpret_cast<double *>(base + L.slots);
+    PD_HIP(hipMemcpyAsync(d_inst, sorted.data(), sizeof(Instance) * count, hipMemcpyHostToDevice, stream));
+    PD_HIP(hipMemcpyAsync(d_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, stream));
+    PD_HIP(hipStreamSynchronize(stream));
+
+    const int teams = L.teams, n_large = L.n_large;
+    Args A;
+    A.inst = d_inst;
+    A.count = count;
+    A.n_large = n_large;
+    A.teams = teams;
+    A.team_size = teams ? L.grid / teams : 1;
+    A.counter = d_counter;
+    A.large_counter = d_large;
+    A.team_ctl = d_team_ctl;
+    A.team_part = d_team_part;
+    A.error = d_error;
+    A.spin_limit = 1ll << 25;
+    A.coef = d_coef;
+    A.slots = d_slots;
+    A.slot_doubles = L.slot_doubles;
+    A.tol = o->tol;
+    A.max_restarts = o->max_restarts;
+    A.res = d_res;
+    A.occ = d_occ;
+
+    // ---- autotune the workgroup size on a sample spread over the cost range
+    double tune_seconds = 0.0;
+    int tuned = 0;
+    if (block == 0) {
+        std::vector<int64_t> key = {count, L.grid, o->krylov};
+        for (int i = 0; i < count; ++i) key.push_back(sorted[i].dim);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            block = it->second;
+        } else {
+            auto ts = std::chrono::steady_clock::now();
+            const int S = std::min(count, kSample);
+            std::vector<Instance> sample(S);
+            for (int q = 0; q < S; ++q) {
+                // quantiles 5% .. 100% of the cost order (largest excluded)
+                int pos = (int)((double)(q + 1) / (S + 1) * (count - 1));
+                sample[q] = sorted[std::min(count - 1, pos + count / 20)];
+            }
+            PD_HIP(hipMemcpyAsync(d_sample, sample.data(), sizeof(Instance) * S, hipMemcpyHostToDevice, stream));
+            Args As = A;
+            As.inst = d_sample;
+            As.count = S;
+            if (L.nslots < L.grid) {
+                As.n_large = S;           // production runs everything on teams
+            } else {
+                As.n_large = 0;           // one workgroup per instance
+                As.teams = 0;
+            }
+            const int trial_grid = As.teams ? L.grid : std::min(S, L.grid);
+            double best = 1e300;
+            const int cands[3] = {128, 256, 512};
+            hipEvent_t e0, e1;
+            PD_HIP(hipEventCreate(&e0));
+            PD_HIP(hipEventCreate(&e1));
+            for (int c : cands) {
+                hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, stream, d_counter, As.n_large, d_large,
+                                   d_team_ctl, kCtlInts * 8, d_error);
+                PD_HIP(hipEventRecord(e0, stream));
+                hipLaunchKernelGGL(batched_kernel, dim3(trial_grid), dim3(c), 0, stream, As);
+                PD_HIP(hipGetLastError());
+                PD_HIP(hipEventRecord(e1, stream));
+                PD_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                PD_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    block = c;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            g_tuned[key] = block;
+            tuned = 1;
+            tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+        }
+    }
+    if (block != 128 && block != 256 && block != 512) return fail(PD_EINVAL, "block must be 0, 128, 256 or 512");
+
+    // ---- one graph: queue reset (a kernel, no memset node) + the persistent solver
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, cap, d_counter, n_large, d_large, d_team_ctl,
+                           kCtlInts * 8, d_error);
+        hipLaunchKernelGGL(batched_kernel, dim3(L.grid), dim3(block), 0, cap, A);
+        e = hipStreamEndCapture(cap, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    auto tk = std::chrono::steady_clock::now();
+    if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    const double kernel_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tk).count();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "batched solve: %s", hipGetErrorString(e));
+    int err_flag = 0;
+    PD_HIP(hipMemcpy(&err_flag, d_error, sizeof(int), hipMemcpyDeviceToHost));
+    if (err_flag) return fail(PD_EDEVICE, "a workgroup team barrier timed out (is another kernel occupying the GPU?)");
+
+    int wall_khz = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+        wall_khz = 100000;
+    const double wall_hz = 1e3 * wall_khz;
+    std::vector<Result> res(count);
+    PD_HIP(hipMemcpy(res.data(), d_res, sizeof(Result) * count, hipMemcpyDeviceToHost));
+    if (occ_out) {
+        PD_HIP(hipMemcpy(occ_out, d_occ, sizeof(double) * L.occ_doubles, hipMemcpyDeviceToHost));
+        for (int i = 0; i < count; ++i)
+            if (flipped[i])
+                for (int q = 0; q < omega[i]; ++q) occ_out[inst[i].occ_off + q] = 2.0 - occ_out[inst[i].occ_off + q];
+    }
+    int nconv = 0;
+    long long total_it = 0;
+    for (int i = 0; i < count; ++i) {
+        E0_out[i] = res[i].E0;
+        nconv += res[i].converged;
+        total_it += res[i].iterations;
+        if (info_out) {
+            pd_lanczos_info &f = info_out[i];
+            std::memset(&f, 0, sizeof(f));
+            f.iterations = res[i].iterations;
+            f.restarts = res[i].restarts;
+            f.converged = res[i].converged;
+            f.residual = res[i].residual;
+            f.seconds = (double)res[i].ticks / wall_hz;
+        }
+    }
+    if (binfo) {
+        binfo->block = block;
+        binfo->grid = L.grid;
+        binfo->tuned = tuned;
+        binfo->tune_seconds = tune_seconds;
+        binfo->kernel_seconds = kernel_seconds;
+        binfo->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        binfo->converged = nconv;
+        binfo->teams = teams;
+        binfo->team_size = A.team_size;
+        binfo->large = n_large;
+        binfo->total_iterations = total_it;
+    }
+    if (nconv < count) return fail(PD_ENOCONV, "%d of %d instances did not converge", count - nconv, count);
+    return PD_OK;
+}
+
+}  // namespace pd

@@ -130,6 +130,13 @@ hipError_t launch_copy(const double *x, int64_t dim, double *out, hipStream_t s)
 hipError_t launch_occupations(int omega, int n, int64_t dim, const double *psi, double *partials,
                               double *occ_dev, hipStream_t s);
 
+// batched.hip
+size_t batched_workspace_bytes(int count, const int *omega, const int *n, const pd_lanczos_opts *o);
+pd_status batched_validate(int count, const int *omega, const int *n, const pd_lanczos_opts *o);
+pd_status batched_run(int count, const int *omega, const int *n, const double *eps_packed, const double *V_packed,
+                      const pd_lanczos_opts *o, int block, void *work, size_t work_bytes, double *E0_out,
+                      double *occ_out, pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream);
+
 // tridiag.cpp: lowest eigenpair of the symmetric tridiagonal (alpha, beta).
 int tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y);
 

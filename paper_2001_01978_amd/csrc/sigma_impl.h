@@ -60,25 +60,111 @@ struct Params {
     T dsum;                    // sum of d (for the mirrored diagonal)
 };
 
+// Stages the binomial table C(p, k) (p < omega, k < ks), the couplings and the
+// pair energies into LDS; returns the three LDS arrays through the pointers.
+template <typename R, typename T>
+__device__ __forceinline__ void stage_tables(unsigned char *smem, int omega, int ks, const T *__restrict__ V,
+                                             const T *__restrict__ d, R *&Ct, T *&Vs, T *&ds) {
+    Ct = reinterpret_cast<R *>(smem);
+    const int ct_elems = omega * ks;
+    Vs = reinterpret_cast<T *>(smem + ((ct_elems * (int)sizeof(R) + 15) & ~15));
+    ds = Vs + omega * omega;
+    for (int i = threadIdx.x; i < ct_elems; i += blockDim.x) {
+        int p = i / ks, k = i - p * ks;
+        Ct[i] = (R)g_binom.v[p][k];
+    }
+    for (int i = threadIdx.x; i < omega * omega; i += blockDim.x) Vs[i] = V[i];
+    for (int i = threadIdx.x; i < omega; i += blockDim.x) ds[i] = d[i];
+}
+
+template <typename R, typename T>
+__host__ __device__ inline size_t table_bytes(int omega, int ks) {
+    return (((size_t)omega * ks * sizeof(R) + 15) & ~size_t(15)) + ((size_t)omega * omega + omega) * sizeof(T);
+}
+
+// (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
+template <typename R, typename T, int NN, bool COMP>
+__device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
+                                       const T *ds, T dsum, const T *__restrict__ x) {
+    const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
+
+    // state of rank rk: greedy, orbits from the top
+    uint64_t s = 0;
+    {
+        R rem = rk;
+        int k = NN;
+        for (int p = omega - 1; p >= 0; --p) {
+            R c = Ct[p * ks + k];
+            if (k > 0 && c <= rem) {
+                s |= 1ull << p;
+                rem -= c;
+                --k;
+            }
+        }
+    }
+
+    // rank + removed-orbit terms, occupied orbits numbered from the top
+    R rup[NN > 0 ? NN : 1], rdn[NN > 0 ? NN : 1];
+    int apos[NN > 0 ? NN : 1];
+    T dacc = T(0);
+    {
+        uint64_t occ = s;
+        R s0 = 0, sm = 0, sp = 0;
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+            const int a = 63 - __clzll((long long)occ);
+            occ &= ~(1ull << a);
+            const int j = NN - r;
+            const R c0 = Ct[a * ks + j], cm = Ct[a * ks + j - 1], cp = Ct[a * ks + j + 1];
+            rup[r] = rk + (sm - s0 - c0);
+            rdn[r] = rk + (s0 - sp - cp);
+            apos[r] = a;
+            s0 += c0;
+            sm += cm;
+            sp += cp;
+            dacc += ds[a];
+        }
+    }
+
+    T acc = (COMP ? (dsum - dacc) : dacc) * x[row];
+    R s0 = 0, sm = 0, sp = 0;
+    int above = 0;
+    for (int p = omega - 1; p >= 0; --p) {
+        if ((s >> p) & 1ull) {
+            const int j = NN - above;
+            s0 += Ct[p * ks + j];
+            sm += Ct[p * ks + j - 1];
+            sp += Ct[p * ks + j + 1];
+            ++above;
+        } else if (NN > 0) {
+            const int t = NN - above;
+            const R bup = s0 - sm + Ct[p * ks + t];
+            const R bdn = sp - s0 + Ct[p * ks + t + 1];
+            const T *Vrow = Vs + p * omega;
+            T xv[NN > 0 ? NN : 1];
+#pragma unroll
+            for (int r = 0; r < NN; ++r) {
+                const R jt = (p > apos[r]) ? (R)(rup[r] + bup) : (R)(rdn[r] + bdn);
+                const int64_t jx = COMP ? (dim - 1 - (int64_t)jt) : (int64_t)jt;
+                xv[r] = x[jx];
+            }
+#pragma unroll
+            for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
+        }
+    }
+    return acc;
+}
+
 template <typename R, typename T, int NN, bool COMP>
 __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int omega = P.omega, ks = P.ks;
-    R *Ct = reinterpret_cast<R *>(smem);
-    const int ct_elems = omega * ks;
-    T *Vs = reinterpret_cast<T *>(smem + ((ct_elems * (int)sizeof(R) + 15) & ~15));
-    T *ds = Vs + omega * omega;
-
-    for (int i = threadIdx.x; i < ct_elems; i += kThreads) {
-        int p = i / ks, k = i - p * ks;
-        Ct[i] = (R)g_binom.v[p][k];
-    }
-    for (int i = threadIdx.x; i < omega * omega; i += kThreads) Vs[i] = P.V[i];
-    for (int i = threadIdx.x; i < omega; i += kThreads) ds[i] = P.d[i];
+    R *Ct;
+    T *Vs, *ds;
+    stage_tables<R, T>(smem, omega, ks, P.V, P.d, Ct, Vs, ds);
     __syncthreads();
 
     const int64_t dim = P.dim;
-    const T *__restrict__ x = P.x;
     // Workgroups are dealt to the 8 XCDs round-robin (workgroup id mod 8).
     // Each XCD walks its own contiguous eighth of the tiles, so the rows in
     // flight on one XCD, and the x lines their hops touch, stay together in
@@ -94,80 +180,13 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
     for (int64_t tile = t_begin; tile < t_end; tile += t_step) {
         const int64_t row = tile * kThreads + threadIdx.x;
         if (row >= dim) continue;
-        const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
-
-        // state of rank rk: greedy, orbits from the top
-        uint64_t s = 0;
-        {
-            R rem = rk;
-            int k = NN;
-            for (int p = omega - 1; p >= 0; --p) {
-                R c = Ct[p * ks + k];
-                if (k > 0 && c <= rem) {
-                    s |= 1ull << p;
-                    rem -= c;
-                    --k;
-                }
-            }
-        }
-
-        // rank + removed-orbit terms, occupied orbits numbered from the top
-        R rup[NN > 0 ? NN : 1], rdn[NN > 0 ? NN : 1];
-        int apos[NN > 0 ? NN : 1];
-        T dacc = T(0);
-        {
-            uint64_t occ = s;
-            R s0 = 0, sm = 0, sp = 0;
-#pragma unroll
-            for (int r = 0; r < NN; ++r) {
-                const int a = 63 - __clzll((long long)occ);
-                occ &= ~(1ull << a);
-                const int j = NN - r;
-                const R c0 = Ct[a * ks + j], cm = Ct[a * ks + j - 1], cp = Ct[a * ks + j + 1];
-                rup[r] = rk + (sm - s0 - c0);
-                rdn[r] = rk + (s0 - sp - cp);
-                apos[r] = a;
-                s0 += c0;
-                sm += cm;
-                sp += cp;
-                dacc += ds[a];
-            }
-        }
-
-        T acc = (COMP ? (P.dsum - dacc) : dacc) * x[row];
-        R s0 = 0, sm = 0, sp = 0;
-        int above = 0;
-        for (int p = omega - 1; p >= 0; --p) {
-            if ((s >> p) & 1ull) {
-                const int j = NN - above;
-                s0 += Ct[p * ks + j];
-                sm += Ct[p * ks + j - 1];
-                sp += Ct[p * ks + j + 1];
-                ++above;
-            } else if (NN > 0) {
-                const int t = NN - above;
-                const R bup = s0 - sm + Ct[p * ks + t];
-                const R bdn = sp - s0 + Ct[p * ks + t + 1];
-                const T *Vrow = Vs + p * omega;
-                T xv[NN > 0 ? NN : 1];
-#pragma unroll
-                for (int r = 0; r < NN; ++r) {
-                    const R jt = (p > apos[r]) ? (R)(rup[r] + bup) : (R)(rdn[r] + bdn);
-                    const int64_t jx = COMP ? (dim - 1 - (int64_t)jt) : (int64_t)jt;
-                    xv[r] = x[jx];
-                }
-#pragma unroll
-                for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
-            }
-        }
-        P.y[row] = acc;
+        P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x);
     }
 }
 
 template <typename R, typename T, int NN, bool COMP>
 hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
-    size_t ct_bytes = ((size_t)P.omega * P.ks * sizeof(R) + 15) & ~size_t(15);
-    size_t smem = ct_bytes + ((size_t)P.omega * P.omega + P.omega) * sizeof(T);
+    const size_t smem = table_bytes<R, T>(P.omega, P.ks);
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
     if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
     hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP>), dim3((unsigned)grid), dim3(kThreads), smem, stream, P);

@@ -42,6 +42,13 @@ class LanczosInfo(ctypes.Structure):
                 ("sigma_seconds_f32", ctypes.c_double)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("grid", ctypes.c_int), ("tuned", ctypes.c_int), ("teams", ctypes.c_int),
+                ("team_size", ctypes.c_int), ("large", ctypes.c_int), ("converged", ctypes.c_int),
+                ("total_iterations", ctypes.c_longlong), ("tune_seconds", ctypes.c_double),
+                ("kernel_seconds", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); the full exported surface of include/pairdiag.h
 P, I, I64, U64, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
 SIGNATURES = {
@@ -64,6 +71,9 @@ SIGNATURES = {
     "pd_occupations_workspace_bytes": (SZ, [P]),
     "pd_occupations": (I, [P, P, P, SZ, P, P]),
     "pd_tridiag_lowest": (I, [I, P, P, ctypes.POINTER(D), P]),
+    "pd_batched_workspace_bytes": (SZ, [I, P, P, ctypes.POINTER(LanczosOpts)]),
+    "pd_lanczos_ground_batched": (I, [I, P, P, P, P, ctypes.POINTER(LanczosOpts), I, P, SZ, P, P,
+                                      ctypes.POINTER(LanczosInfo), ctypes.POINTER(BatchInfo), P]),
 }
 
 _lib = None
@@ -288,3 +298,63 @@ def lanczos_ground(basis: Basis, eps, V, x0=None, want_psi=True, workspace=None,
                        iterations_f32=info.iterations_f32, restarts=info.restarts, converged=bool(info.converged),
                        residual=info.residual, monopole_min=info.monopole_min, seconds=info.seconds,
                        sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32, status=st)
+
+
+@dataclass
+class BatchResult:
+    E0: np.ndarray
+    occ: list
+    iterations: np.ndarray
+    restarts: np.ndarray
+    converged: np.ndarray
+    residual: np.ndarray
+    seconds: np.ndarray
+    info: dict
+    status: int
+
+
+def _pack_batch(instances):
+    om = np.array([int(i[0]) for i in instances], dtype=np.int32)
+    n = np.array([int(i[1]) for i in instances], dtype=np.int32)
+    eps = np.concatenate([np.ascontiguousarray(i[2], dtype=np.float64).reshape(-1) for i in instances])
+    V = np.concatenate([np.ascontiguousarray(i[3], dtype=np.float64).reshape(-1) for i in instances])
+    return om, n, eps, V
+
+
+def batched_workspace_bytes(instances, krylov=20, **kw) -> int:
+    om, n, _, _ = _pack_batch(instances)
+    o = make_opts(krylov=krylov, **kw)
+    return int(load().pd_batched_workspace_bytes(len(om), _hp(om), _hp(n), ctypes.byref(o)))
+
+
+def lanczos_ground_batched(instances, krylov=20, tol=1e-10, max_restarts=1000, seed=0, block=0,
+                           workspace=None, device="cuda", stream=None) -> BatchResult:
+    """Ground states of many (omega, n, eps, V) instances in one persistent launch
+    (pd_lanczos_ground_batched)."""
+    L = load()
+    om, n, eps, V = _pack_batch(instances)
+    count = len(om)
+    o = make_opts(krylov=krylov, tol=tol, max_restarts=max_restarts, seed=seed)
+    nb = L.pd_batched_workspace_bytes(count, _hp(om), _hp(n), ctypes.byref(o))
+    if nb == 0:
+        raise PairDiagError(PD_EINVAL, L.pd_last_error().decode())
+    if workspace is None:
+        buf, off = device_buffer(nb, device)
+    else:
+        buf, off = workspace
+    E0 = np.empty(count)
+    occ = np.empty(int(om.sum()))
+    infos = (LanczosInfo * count)()
+    bi = BatchInfo()
+    st = L.pd_lanczos_ground_batched(count, _hp(om), _hp(n), _hp(eps), _hp(V), ctypes.byref(o), block,
+                                     ctypes.c_void_p(buf.data_ptr() + off), nb, _hp(E0), _hp(occ), infos,
+                                     ctypes.byref(bi), _stream(stream))
+    _check(st, allow=(PD_ENOCONV,))
+    splits = np.cumsum(om)[:-1]
+    return BatchResult(E0=E0, occ=np.split(occ, splits),
+                       iterations=np.array([f.iterations for f in infos]),
+                       restarts=np.array([f.restarts for f in infos]),
+                       converged=np.array([bool(f.converged) for f in infos]),
+                       residual=np.array([f.residual for f in infos]),
+                       seconds=np.array([f.seconds for f in infos]),
+                       info={k: getattr(bi, k) for k, _ in BatchInfo._fields_}, status=st)

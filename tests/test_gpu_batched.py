@@ -1,0 +1,96 @@
+"""GPU parity of the batched persistent solver: every instance against the
+oracle (dense diagonalisation where small) and against the single-instance
+GPU path, E0 within 1e-10 relative, occupations within 1e-8."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2001_01978_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pdg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2001_01978_amd import pairdiag
+    pairdiag.load()
+    return pairdiag
+
+
+def _small_family(count, seed0, max_omega):
+    out = []
+    s = seed0
+    while len(out) < count:
+        inst = inputs.family3_instance(s)
+        s += 1
+        if inst[0] <= max_omega:
+            out.append(inst)
+    return out
+
+
+def test_batched_small_vs_oracle_dense(pdg, oracle_mod):
+    insts = _small_family(40, 1000, 13)
+    r = pdg.lanczos_ground_batched(insts, krylov=20, tol=1e-11, seed=3)
+    assert r.status == pdg.PD_OK and r.converged.all()
+    for (om, n, eps, V), E, occ in zip(insts, r.E0, r.occ):
+        E0, _, occ0, _ = oracle_mod.dense_ground(om, n, eps, V)
+        assert abs(E - E0) <= 1e-10 * abs(E0), (om, n, E, E0)
+        assert np.allclose(occ, occ0, atol=1e-8)
+
+
+@pytest.mark.parametrize("block", [128, 256, 512])
+def test_batched_block_sizes_agree_with_single_path(pdg, block):
+    insts = _small_family(24, 5000, 18) + [inputs.family3_instance(7, omega=20, n=9)]
+    r = pdg.lanczos_ground_batched(insts, krylov=16, tol=1e-10, seed=11, block=block)
+    assert r.converged.all()
+    for (om, n, eps, V), E, occ in zip(insts, r.E0, r.occ):
+        b = pdg.Basis(om, n, store_states=False)
+        s = pdg.lanczos_ground(b, eps, V, krylov=16, tol=1e-10, start="random", seed=1, want_psi=False)
+        assert abs(E - s.E0) <= 1e-10 * abs(s.E0)
+        assert np.allclose(occ, s.occ, atol=1e-8)
+
+
+def test_batched_family_with_large_instances(pdg):
+    """The batched family at its full size range: dims from ~1e2 to 2.7e6 (Omega=24, n=12)."""
+    insts = [inputs.family3_instance(s) for s in range(96)]
+    insts.append(inputs.family3_instance(123, omega=24, n=12))
+    r = pdg.lanczos_ground_batched(insts, krylov=20, tol=1e-10, seed=0)
+    assert r.status == pdg.PD_OK and r.converged.all()
+    assert r.info["grid"] >= 1 and r.info["block"] in (128, 256, 512)
+    dims = np.array([math.comb(i[0], i[1]) for i in insts])
+    check = list(np.argsort(-dims)[:3]) + list(range(0, 96, 12))
+    for q in check:
+        om, n, eps, V = insts[q]
+        b = pdg.Basis(om, n, store_states=False)
+        s = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=2, want_psi=False)
+        assert abs(r.E0[q] - s.E0) <= 1e-10 * abs(s.E0), (q, om, n)
+        assert np.allclose(r.occ[q], s.occ, atol=1e-8)
+        assert math.isclose(r.occ[q].sum(), 2 * n, abs_tol=1e-8)
+
+
+def test_batched_edge_instances(pdg, oracle_mod):
+    rng = np.random.default_rng(4)
+    insts = []
+    for om, n in [(1, 0), (1, 1), (2, 1), (4, 2), (6, 6), (8, 0), (9, 8), (12, 1), (30, 2), (32, 31)]:
+        eps = rng.uniform(0, 3, om)
+        G = rng.uniform(0.1, 0.6, (om, om))
+        insts.append((om, n, eps, -(G + G.T) / 2))
+    r = pdg.lanczos_ground_batched(insts, krylov=12, tol=1e-11, block=256)
+    assert r.converged.all()
+    for (om, n, eps, V), E in zip(insts, r.E0):
+        E0, *_ = oracle_mod.dense_ground(om, n, eps, V)
+        assert abs(E - E0) <= 1e-10 * max(abs(E0), 1.0)
+
+
+def test_batched_noconvergence_and_errors(pdg):
+    insts = _small_family(6, 77, 14)
+    r = pdg.lanczos_ground_batched(insts, krylov=4, tol=0.0, max_restarts=1, block=128)
+    assert r.status == pdg.PD_ENOCONV and not r.converged.any()
+    assert np.all(np.isfinite(r.E0))
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_batched([(40, 3, np.zeros(40), -np.ones((40, 40)))])
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_batched(insts, krylov=40)
