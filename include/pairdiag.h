@@ -124,6 +124,8 @@ typedef struct {
     int mode;          /* 0 restarted (default), 1 single cycle */
     int start;         /* pd_start; default PD_START_E1 */
     uint64_t seed;     /* PD_START_RANDOM stream */
+    int fallback;      /* PD_START_USER only: 1 = also try the RANDOM start and keep the one
+                          with the lower Rayleigh quotient (two extra products) */
     int precision;     /* PD_F64 (default) or PD_F32: FP32 products for Krylov steps
                           k >= 2 of every cycle; the first step of each cycle, all
                           dot products, the recurrence, the reorthogonalisation, the
@@ -141,6 +143,7 @@ typedef struct {
     double seconds;      /* wall time of the call */
     double sigma_seconds_f64;  /* summed device time of the FP64 products (HIP events) */
     double sigma_seconds_f32;  /* summed device time of the FP32 products (HIP events) */
+    int fallback_used;         /* 1 if the fallback replaced the caller's start vector */
 } pd_lanczos_info;
 
 void pd_lanczos_default_opts(pd_lanczos_opts *o);
@@ -207,6 +210,37 @@ pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, c
                                     const double *V_packed, const pd_lanczos_opts *o, int block,
                                     void *work_dev, size_t work_bytes, double *E0_out, double *occ_out,
                                     pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream);
+
+/* ------------------------------------------------------------------ warm start
+ * A small network maps an instance to one logit l_i per orbit; sigmoid(l_i)
+ * estimates the half occupation <N_i>/2.  Taking it as the BCS v_i^2 gives
+ * pair amplitudes v_i/u_i = exp(l_i/2), and the number-projected product state
+ *     psi_k = prod_{i occupied in k} exp(l_i / 2)
+ * is the start vector (computed as exp((sum_occ l_i - L)/2), L = sum of the n
+ * largest l_i, so entries lie in (0, 1]; not normalised).
+ * logits_dev: device, omega floats.  x0_dev: device, dim doubles.  Synchronises. */
+pd_status pd_warm_start(pd_basis b, const float *logits_dev, double *x0_dev, hipStream_t stream);
+
+/* Network: in -> h1 -> h2 -> out, GELU (tanh form) after the two hidden
+ * layers, linear output.  Parameters: one FP32 device array, in this order:
+ * W1 (in x h1, row-major), b1 (h1), W2 (h1 x h2), b2 (h2), W3 (h2 x out), b3 (out).
+ * Activations are row-major (batch x features).  Products run on BF16 matrix
+ * cores (operands rounded from FP32, FP32 accumulation).
+ * Loss: mean over batch x out of (sigmoid(logit) - target)^2. */
+typedef struct { int in, h1, h2, out; } pd_mlp_shape;
+size_t pd_mlp_param_count(const pd_mlp_shape *s);
+size_t pd_mlp_workspace_bytes(const pd_mlp_shape *s, int batch);
+/* logits_dev: batch x out (device). */
+pd_status pd_mlp_forward(const pd_mlp_shape *s, const float *params_dev, const float *X_dev, int batch,
+                         void *work_dev, size_t work_bytes, float *logits_dev, hipStream_t stream);
+/* Forward, loss and backward: grads_dev (param_count floats) receives d loss / d params,
+ * loss_dev (one float, device) the loss. */
+pd_status pd_mlp_backward(const pd_mlp_shape *s, const float *params_dev, const float *X_dev,
+                          const float *target_dev, int batch, void *work_dev, size_t work_bytes,
+                          float *grads_dev, float *loss_dev, hipStream_t stream);
+/* Adam (Kingma & Ba) with bias correction, step >= 1; m, v: state arrays of count floats. */
+pd_status pd_mlp_adam(int64_t count, float *params_dev, const float *grads_dev, float *m_dev, float *v_dev,
+                      int step, float lr, float beta1, float beta2, float eps, hipStream_t stream);
 
 /* ------------------------------------------------------------------ host utility
  * Lowest eigenpair of the m x m symmetric tridiagonal matrix with diagonal

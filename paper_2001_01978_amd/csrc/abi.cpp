@@ -122,6 +122,70 @@ pd_status check_basis(pd_basis b) {
 }  // namespace
 }  // namespace pd
 
+namespace pd {
+namespace {
+struct MlpLayout {
+    size_t Z1, H1, Z2, H2, L, dL, G2, G1, part, loss, total;
+};
+bool valid_shape(const pd_mlp_shape *s) {
+    return s && s->in >= 1 && s->h1 >= 1 && s->h2 >= 1 && s->out >= 1 && s->in <= 65536 && s->h1 <= 65536 &&
+           s->h2 <= 65536 && s->out <= 65536;
+}
+MlpLayout mlp_layout(const pd_mlp_shape *s, int batch) {
+    MlpLayout L;
+    size_t off = 0;
+    auto take = [&](size_t floats) {
+        size_t o = off;
+        off += align256(floats * sizeof(float));
+        return o;
+    };
+    const size_t B = (size_t)batch;
+    L.Z1 = take(B * s->h1);
+    L.H1 = take(B * s->h1);
+    L.Z2 = take(B * s->h2);
+    L.H2 = take(B * s->h2);
+    L.L = take(B * s->out);
+    L.dL = take(B * s->out);
+    L.G2 = take(B * s->h2);
+    L.G1 = take(B * s->h1);
+    L.part = take(64);
+    L.loss = take(1);
+    L.total = off;
+    return L;
+}
+struct MlpParams {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+template <typename P>
+P mlp_split(const pd_mlp_shape *s, P base, P *W1, P *b1, P *W2, P *b2, P *W3, P *b3) {
+    P q = base;
+    *W1 = q;
+    q += (size_t)s->in * s->h1;
+    *b1 = q;
+    q += s->h1;
+    *W2 = q;
+    q += (size_t)s->h1 * s->h2;
+    *b2 = q;
+    q += s->h2;
+    *W3 = q;
+    q += (size_t)s->h2 * s->out;
+    *b3 = q;
+    q += s->out;
+    return q;
+}
+hipError_t mlp_forward_impl(const pd_mlp_shape *s, const float *P, const float *X, int B, unsigned char *w,
+                            const MlpLayout &L, float *logits, hipStream_t st) {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    mlp_split<const float *>(s, P, &W1, &b1, &W2, &b2, &W3, &b3);
+    float *Z1 = (float *)(w + L.Z1), *H1 = (float *)(w + L.H1), *Z2 = (float *)(w + L.Z2), *H2 = (float *)(w + L.H2);
+    hipError_t e = launch_gemm_bf16(false, false, B, s->h1, s->in, X, s->in, W1, s->h1, Z1, s->h1, b1, 2, H1, st);
+    if (e == hipSuccess) e = launch_gemm_bf16(false, false, B, s->h2, s->h1, H1, s->h1, W2, s->h2, Z2, s->h2, b2, 2, H2, st);
+    if (e == hipSuccess) e = launch_gemm_bf16(false, false, B, s->out, s->h2, H2, s->h2, W3, s->out, logits, s->out, b3, 1, nullptr, st);
+    return e;
+}
+}  // namespace
+}  // namespace pd
+
 using namespace pd;
 
 extern "C" {
@@ -258,6 +322,7 @@ void pd_lanczos_default_opts(pd_lanczos_opts *o) {
     o->start = PD_START_E1;
     o->seed = 0;
     o->precision = PD_F64;
+    o->fallback = 0;
     o->verbose = 0;
 }
 
@@ -345,6 +410,113 @@ pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, c
     if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
     return batched_run(count, omega, n, eps_packed, V_packed, o, block, work_dev, work_bytes, E0_out, occ_out,
                        info_out, binfo, stream);
+}
+
+pd_status pd_warm_start(pd_basis b, const float *logits_dev, double *x0_dev, hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if ((st = check_sigma_range(b)) != PD_OK) return st;
+    if ((st = check_device_ptr(logits_dev, "logits_dev", b->omega * sizeof(float))) != PD_OK) return st;
+    if ((st = check_device_ptr(x0_dev, "x0_dev", b->dim * sizeof(double))) != PD_OK) return st;
+    float l[64];
+    hipError_t e = hipMemcpyAsync(l, logits_dev, b->omega * sizeof(float), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "logits copy: %s", hipGetErrorString(e));
+    double ls[64];
+    for (int i = 0; i < b->omega; ++i) {
+        if (!std::isfinite(l[i])) return fail(PD_EINVAL, "logit %d is not finite", i);
+        ls[i] = l[i];
+    }
+    std::sort(ls, ls + b->omega, [](double a, double c) { return a > c; });
+    double lmax = 0.0;
+    for (int i = 0; i < b->n; ++i) lmax += ls[i];
+    e = launch_warm_expand(b->omega, b->n, b->dim, logits_dev, lmax, x0_dev, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "warm start: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+
+size_t pd_mlp_param_count(const pd_mlp_shape *s) {
+    if (!valid_shape(s)) return 0;
+    return (size_t)s->in * s->h1 + s->h1 + (size_t)s->h1 * s->h2 + s->h2 + (size_t)s->h2 * s->out + s->out;
+}
+
+size_t pd_mlp_workspace_bytes(const pd_mlp_shape *s, int batch) {
+    if (!valid_shape(s) || batch < 1) return 0;
+    return mlp_layout(s, batch).total;
+}
+
+pd_status pd_mlp_forward(const pd_mlp_shape *s, const float *params_dev, const float *X_dev, int batch, void *work_dev,
+                         size_t work_bytes, float *logits_dev, hipStream_t stream) {
+    if (!valid_shape(s) || batch < 1) return fail(PD_EINVAL, "bad network shape or batch");
+    MlpLayout L = mlp_layout(s, batch);
+    if (work_bytes < L.total) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
+    pd_status st;
+    if ((st = check_device_ptr(params_dev, "params_dev", pd_mlp_param_count(s) * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(X_dev, "X_dev", (size_t)batch * s->in * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(work_dev, "work_dev", L.total)) != PD_OK) return st;
+    if ((st = check_device_ptr(logits_dev, "logits_dev", (size_t)batch * s->out * 4)) != PD_OK) return st;
+    hipError_t e = mlp_forward_impl(s, params_dev, X_dev, batch, (unsigned char *)work_dev, L, logits_dev, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "mlp forward: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+pd_status pd_mlp_backward(const pd_mlp_shape *s, const float *params_dev, const float *X_dev, const float *target_dev,
+                          int batch, void *work_dev, size_t work_bytes, float *grads_dev, float *loss_dev,
+                          hipStream_t stream) {
+    if (!valid_shape(s) || batch < 1) return fail(PD_EINVAL, "bad network shape or batch");
+    MlpLayout L = mlp_layout(s, batch);
+    if (work_bytes < L.total) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
+    const size_t np = pd_mlp_param_count(s);
+    pd_status st;
+    if ((st = check_device_ptr(params_dev, "params_dev", np * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(X_dev, "X_dev", (size_t)batch * s->in * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(target_dev, "target_dev", (size_t)batch * s->out * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(work_dev, "work_dev", L.total)) != PD_OK) return st;
+    if ((st = check_device_ptr(grads_dev, "grads_dev", np * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(loss_dev, "loss_dev", 4)) != PD_OK) return st;
+    unsigned char *w = (unsigned char *)work_dev;
+    float *Lg = (float *)(w + L.L), *dL = (float *)(w + L.dL);
+    hipError_t e = mlp_forward_impl(s, params_dev, X_dev, batch, w, L, Lg, stream);
+    if (e == hipSuccess) e = launch_mlp_loss(batch * s->out, Lg, target_dev, dL, (float *)(w + L.part), loss_dev, stream);
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    mlp_split<const float *>(s, params_dev, &W1, &b1, &W2, &b2, &W3, &b3);
+    float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
+    mlp_split<float *>(s, grads_dev, &gW1, &gb1, &gW2, &gb2, &gW3, &gb3);
+    float *Z1 = (float *)(w + L.Z1), *H1 = (float *)(w + L.H1), *Z2 = (float *)(w + L.Z2), *H2 = (float *)(w + L.H2);
+    float *G2 = (float *)(w + L.G2), *G1 = (float *)(w + L.G1);
+    const int B = batch;
+    // layer 3
+    if (e == hipSuccess) e = launch_gemm_bf16(true, false, s->h2, s->out, B, H2, s->h2, dL, s->out, gW3, s->out, nullptr, 0, nullptr, stream);
+    if (e == hipSuccess) e = launch_colsum(B, s->out, dL, gb3, stream);
+    if (e == hipSuccess) e = launch_gemm_bf16(false, true, B, s->h2, s->out, dL, s->out, W3, s->out, G2, s->h2, nullptr, 0, nullptr, stream);
+    if (e == hipSuccess) e = launch_gelu_back(B * s->h2, Z2, G2, stream);
+    // layer 2
+    if (e == hipSuccess) e = launch_gemm_bf16(true, false, s->h1, s->h2, B, H1, s->h1, G2, s->h2, gW2, s->h2, nullptr, 0, nullptr, stream);
+    if (e == hipSuccess) e = launch_colsum(B, s->h2, G2, gb2, stream);
+    if (e == hipSuccess) e = launch_gemm_bf16(false, true, B, s->h1, s->h2, G2, s->h2, W2, s->h2, G1, s->h1, nullptr, 0, nullptr, stream);
+    if (e == hipSuccess) e = launch_gelu_back(B * s->h1, Z1, G1, stream);
+    // layer 1
+    if (e == hipSuccess) e = launch_gemm_bf16(true, false, s->in, s->h1, B, X_dev, s->in, G1, s->h1, gW1, s->h1, nullptr, 0, nullptr, stream);
+    if (e == hipSuccess) e = launch_colsum(B, s->h1, G1, gb1, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "mlp backward: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+pd_status pd_mlp_adam(int64_t count, float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int step,
+                      float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+    if (count < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+        return fail(PD_EINVAL, "bad Adam arguments");
+    pd_status st;
+    if ((st = check_device_ptr(params_dev, "params_dev", count * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(grads_dev, "grads_dev", count * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(m_dev, "m_dev", count * 4)) != PD_OK) return st;
+    if ((st = check_device_ptr(v_dev, "v_dev", count * 4)) != PD_OK) return st;
+    hipError_t e = launch_adam((int)count, params_dev, grads_dev, m_dev, v_dev, lr, beta1, beta2, eps, step, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "adam: %s", hipGetErrorString(e));
+    return PD_OK;
 }
 
 int pd_tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y) {

@@ -166,6 +166,30 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
         PD_HIP(launch_scale(w, dim, sc, Q, x32, s));
     }
 
+    // Fallback for a caller-supplied start: also try the RANDOM start and keep
+    // the vector with the lower Rayleigh quotient (two FP64 products).
+    if (o->start == PD_START_USER && o->fallback && m >= 2) {
+        double rq[2];
+        for (int t = 0; t < 2; ++t) {
+            double *q = Q + (size_t)t * ld;
+            if (t == 1) {
+                PD_HIP(launch_fill_random(o->seed, dim, w, s));
+                PD_HIP(launch_norm_sum(w, dim, partials, scal + kOffNrm, scal + kOffSum, s));
+                PD_HIP(dev.fetch(kOffNrm, 1));
+                PD_HIP(launch_scale(w, dim, 1.0 / std::sqrt(dev.host[kOffNrm]), q, nullptr, s));
+            }
+            PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, q, p, s, dsum64, dsum32));
+            ++info.iterations;
+            PD_HIP(launch_gemvt(q, ld, 1, dim, p, partials, scal + kOffC, s));
+            PD_HIP(dev.fetch(kOffC, 1));
+            rq[t] = dev.host[kOffC];
+        }
+        if (rq[1] < rq[0]) {
+            PD_HIP(launch_scale(Q + ld, dim, 1.0, Q, x32, s));
+            info.fallback_used = 1;
+        }
+    }
+
     // HIP events around every product: its device time, read after the step's sync
     struct Events {
         hipEvent_t a = nullptr, b = nullptr;

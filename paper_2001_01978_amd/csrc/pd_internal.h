@@ -137,6 +137,18 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
                       const pd_lanczos_opts *o, int block, void *work, size_t work_bytes, double *E0_out,
                       double *occ_out, pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream);
 
+// mlp.hip
+hipError_t launch_gemm_bf16(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                            float *C, int ldc, const float *bias, int epilogue, float *H, hipStream_t s);
+hipError_t launch_mlp_loss(int count, const float *logits, const float *target, float *dl, float *partial,
+                           float *loss, hipStream_t s);
+hipError_t launch_gelu_back(int count, const float *z, float *g, hipStream_t s);
+hipError_t launch_colsum(int M, int N, const float *G, float *db, hipStream_t s);
+hipError_t launch_adam(int count, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t s);
+hipError_t launch_warm_expand(int omega, int n, int64_t dim, const float *logits, double lmax, double *psi,
+                              hipStream_t s);
+
 // tridiag.cpp: lowest eigenpair of the symmetric tridiagonal (alpha, beta).
 int tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y);
 

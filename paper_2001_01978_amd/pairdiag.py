@@ -32,14 +32,14 @@ _STATUS = {0: "PD_OK", 1: "PD_EINVAL", 2: "PD_ERANGE", 3: "PD_ENOMEM", 4: "PD_ED
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("krylov", ctypes.c_int), ("tol", ctypes.c_double), ("max_restarts", ctypes.c_int),
                 ("mode", ctypes.c_int), ("start", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("precision", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("precision", ctypes.c_int), ("verbose", ctypes.c_int)]
 
 
 class LanczosInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("iterations_f32", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("converged", ctypes.c_int), ("residual", ctypes.c_double), ("monopole_min", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("sigma_seconds_f64", ctypes.c_double),
-                ("sigma_seconds_f32", ctypes.c_double)]
+                ("sigma_seconds_f32", ctypes.c_double), ("fallback_used", ctypes.c_int)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -47,6 +47,10 @@ class BatchInfo(ctypes.Structure):
                 ("team_size", ctypes.c_int), ("large", ctypes.c_int), ("converged", ctypes.c_int),
                 ("total_iterations", ctypes.c_longlong), ("tune_seconds", ctypes.c_double),
                 ("kernel_seconds", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class MlpShape(ctypes.Structure):
+    _fields_ = [("inp", ctypes.c_int), ("h1", ctypes.c_int), ("h2", ctypes.c_int), ("out", ctypes.c_int)]
 
 
 # name -> (restype, argtypes); the full exported surface of include/pairdiag.h
@@ -71,6 +75,13 @@ SIGNATURES = {
     "pd_occupations_workspace_bytes": (SZ, [P]),
     "pd_occupations": (I, [P, P, P, SZ, P, P]),
     "pd_tridiag_lowest": (I, [I, P, P, ctypes.POINTER(D), P]),
+    "pd_warm_start": (I, [P, P, P, P]),
+    "pd_mlp_param_count": (SZ, [ctypes.POINTER(MlpShape)]),
+    "pd_mlp_workspace_bytes": (SZ, [ctypes.POINTER(MlpShape), I]),
+    "pd_mlp_forward": (I, [ctypes.POINTER(MlpShape), P, P, I, P, SZ, P, P]),
+    "pd_mlp_backward": (I, [ctypes.POINTER(MlpShape), P, P, P, I, P, SZ, P, P, P]),
+    "pd_mlp_adam": (I, [I64, P, P, P, P, I, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_float, ctypes.c_float, P]),
     "pd_batched_workspace_bytes": (SZ, [I, P, P, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_ground_batched": (I, [I, P, P, P, P, ctypes.POINTER(LanczosOpts), I, P, SZ, P, P,
                                       ctypes.POINTER(LanczosInfo), ctypes.POINTER(BatchInfo), P]),
@@ -224,6 +235,17 @@ class Basis:
         _check(load().pd_sigma(self._h, _hp(eps), _hp(V), dt, _dptr(x), _dptr(y), _stream(stream)))
         return y
 
+    def warm_start(self, logits, x0=None, stream=None):
+        """Number-projected product start vector from per-orbit logits (pd_warm_start)."""
+        torch = _torch()
+        logits = logits.to(device=self._buf.device, dtype=torch.float32).contiguous()
+        if logits.numel() != self.omega:
+            raise ValueError("one logit per orbit")
+        if x0 is None:
+            x0 = torch.empty(self.dim, dtype=torch.float64, device=self._buf.device)
+        _check(load().pd_warm_start(self._h, _dptr(logits), _dptr(x0), _stream(stream)))
+        return x0
+
     def occupations(self, psi, stream=None):
         L = load()
         nb = L.pd_occupations_workspace_bytes(self._h)
@@ -248,11 +270,12 @@ class GroundState:
     seconds: float
     sigma_seconds_f64: float
     sigma_seconds_f32: float
+    fallback_used: bool
     status: int
 
 
 def make_opts(krylov=50, tol=1e-10, max_restarts=1000, mode=0, start="e1", seed=0, precision="f64",
-              verbose=False) -> LanczosOpts:
+              verbose=False, fallback=False) -> LanczosOpts:
     o = LanczosOpts()
     load().pd_lanczos_default_opts(ctypes.byref(o))
     o.krylov, o.tol, o.max_restarts, o.mode = krylov, tol, max_restarts, mode
@@ -260,6 +283,7 @@ def make_opts(krylov=50, tol=1e-10, max_restarts=1000, mode=0, start="e1", seed=
     o.seed = seed
     o.precision = PD_F32 if precision in ("f32", "mixed", PD_F32) else PD_F64
     o.verbose = int(verbose)
+    o.fallback = int(fallback)
     return o
 
 
@@ -297,7 +321,8 @@ def lanczos_ground(basis: Basis, eps, V, x0=None, want_psi=True, workspace=None,
     return GroundState(E0=e0.value, psi=psi, occ=occ, iterations=info.iterations,
                        iterations_f32=info.iterations_f32, restarts=info.restarts, converged=bool(info.converged),
                        residual=info.residual, monopole_min=info.monopole_min, seconds=info.seconds,
-                       sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32, status=st)
+                       sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32,
+                       fallback_used=bool(info.fallback_used), status=st)
 
 
 @dataclass
