@@ -456,10 +456,11 @@ double instance_cost(int omega, int n, int krylov) {
 
 // Schedule: with a full grid (a multiple of 8 workgroups), 8 teams of grid/8
 // workgroups first solve the costliest instances (sorted order), then every
-// workgroup drains the rest alone.  The split is chosen on the cost model:
+// workgroup drains the rest alone.  The split s comes from the cost model:
 // phase 1 takes (cost of the first s) / (grid * team efficiency), phase 2 the
 // larger of (cost of the rest) / grid and one remaining instance times 3
-// (iteration counts of equal-size instances differ by that much).
+// (iteration counts of equal-size instances differ by that much); the largest
+// s within 10% of the best predicted time is taken.
 void plan_schedule(int count, const int *omega, const int *n, int krylov, int grid, const std::vector<int> &order,
                    int *teams, int *n_large) {
     *teams = 0;
@@ -468,18 +469,23 @@ void plan_schedule(int count, const int *omega, const int *n, int krylov, int gr
     std::vector<double> cost(count);
     double total = 0.0;
     for (int i = 0; i < count; ++i) total += (cost[i] = instance_cost(omega[i], n[i], krylov));
-    const double team_eff = 0.85;  // barriers and shorter rows per workgroup
+    const double team_eff = 0.95;  // barriers and shorter rows per workgroup
+    std::vector<double> t(count + 1);
     double best = 1e300, done = 0.0;
     for (int split = 0; split <= count; ++split) {
         const double rest = total - done;
         const double largest_rest = split < count ? cost[order[split]] : 0.0;
-        const double t = done / (grid * team_eff) + std::max(rest / grid, 3.0 * largest_rest);
-        if (t < best) {
-            best = t;
-            *n_large = split;
-        }
+        t[split] = done / (grid * team_eff) + std::max(rest / grid, 3.0 * largest_rest);
+        best = std::min(best, t[split]);
         if (split < count) done += cost[order[split]];
     }
+    // the most team work within 10% of the best: teams keep a single slow
+    // instance off the critical path and need one Krylov slot per team only
+    for (int split = count; split >= 0; --split)
+        if (t[split] <= 1.1 * best) {
+            *n_large = split;
+            break;
+        }
     if (*n_large > 0) *teams = 8;
 }
 
@@ -666,8 +672,8 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
             Args As = A;
             As.inst = d_sample;
             As.count = S;
-            if (L.nslots < L.grid) {
-                As.n_large = S;           // production runs everything on teams
+            if (L.teams > 0) {
+                As.n_large = S;           // the sample runs on teams (short trials)
             } else {
                 As.n_large = 0;           // one workgroup per instance
                 As.teams = 0;

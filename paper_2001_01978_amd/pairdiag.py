@@ -91,9 +91,14 @@ _lib = None
 
 
 def load():
-    """Loads libpairdiag.so (raises if it was not built)."""
+    """Loads libpairdiag.so (raises if it was not built).
+
+    torch is imported first: the library's HIP runtime dependency
+    (libamdhip64.so.7) then resolves to the runtime torch already loaded, so
+    the process holds one HIP runtime that both use."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see docstring)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_01978_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
