@@ -9,9 +9,11 @@ acceptance, occupations) in mixed precision (FP32 products, FP64 everything
 else) to an FP64-checked residual of 1e-10, from a seeded random start.
 
 value = sigma non-zeros generated per second of the timed solves (whole job).
-Also reported: time-to-E0 for plain FP64 and mixed precision, per-product
-sigma rates, the roofline of the dominant kernel (the FP32 sigma) from its
-HIP-event durations inside the timed region, and the oracle's CPU rate on a
+Also reported: time-to-E0 for plain FP64, mixed precision and the learned
+warm start (mixed precision from the network's product-state start), per-
+product sigma rates, the roofline of the dominant kernel (the FP32 sigma)
+from its HIP-event durations inside the timed region, the batched solver on
+4096 instances of the uneven random family, and the oracle's CPU rate on a
 bounded sample of rows of the same instance.
 """
 import argparse
@@ -37,6 +39,9 @@ def parse():
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 time-to-E0 solve")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned-warm-start time-to-E0 solve")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-instance batched solve")
+    ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size in rows (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=5)
@@ -198,6 +203,43 @@ def main():
         plain = r64
         log(f"plain f64: E0={r64.E0:.12f} products={r64.iterations} {r64.seconds:.2f} s")
 
+    warm_r, warm_info = None, None
+    wpath = os.path.join(ROOT, "paper_2001_01978_amd", "weights", f"warm_o{om}_n{n}.npz")
+    if not args.no_warm and os.path.exists(wpath):
+        from paper_2001_01978_amd import warm
+        t = time.perf_counter()
+        net = warm.WarmNet.load(wpath)
+        lo = net.logits(om, eps, V)
+        x0 = basis.warm_start(torch.tensor(lo, dtype=torch.float32))
+        warm_r = pairdiag.lanczos_ground(basis, eps, V, x0=x0, fallback=True, precision="f32", workspace=ws,
+                                         krylov=args.krylov, tol=args.tol, want_psi=False)
+        torch.cuda.synchronize()
+        warm_total = time.perf_counter() - t
+        warm_info = dict(weights=os.path.relpath(wpath, ROOT), seconds_including_network=warm_total,
+                         fallback_used=warm_r.fallback_used)
+        log(f"warm (mixed): E0={warm_r.E0:.12f} products={warm_r.iterations} {warm_total:.2f} s incl. network")
+
+    batched = None
+    if not args.no_batched:
+        insts = [inputs.family3_instance(s) for s in range(args.batched_count)]
+        dims = np.array([math.comb(i[0], i[1]) for i in insts])
+        Ks = np.array([i[1] * (i[0] - i[1]) for i in insts])
+        del ws
+        torch.cuda.empty_cache()
+        rb = pairdiag.lanczos_ground_batched(insts, krylov=20, tol=args.tol)   # includes the autotuner
+        rb = pairdiag.lanczos_ground_batched(insts, krylov=20, tol=args.tol)   # tuned
+        bnnz = float((rb.iterations * dims * Ks).sum())
+        batched = dict(workload=f"{args.batched_count} instances, omega ~ U{{10..24}}, n ~ U{{ceil(omega/4)..omega/2}}, "
+                                f"eps ~ U[0,omega), G_ij = G0(1+0.2u), G0 ~ U[0.1,0.6), seeds 0..{args.batched_count-1}",
+                       sum_dim=int(dims.sum()), max_dim=int(dims.max()), converged=int(rb.converged.sum()),
+                       seconds=rb.info["kernel_seconds"], call_seconds=rb.info["seconds"],
+                       instances_per_s=args.batched_count / rb.info["kernel_seconds"],
+                       products=int(rb.iterations.sum()), nnz_per_s=bnnz / rb.info["kernel_seconds"],
+                       block=rb.info["block"], teams=rb.info["teams"], team_size=rb.info["team_size"],
+                       team_instances=rb.info["large"], status=pairdiag._STATUS.get(rb.status))
+        log(f"batched: {batched['converged']}/{args.batched_count} converged in {batched['seconds']:.2f} s, "
+            f"{batched['nnz_per_s']:.3e} nnz/s")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -228,11 +270,15 @@ def main():
                      "algorithmic_bytes_per_launch": balg32,
                      "avg_launch_ms": avg32 * 1e3},
         "cpu_baseline": cpu,
-        "time_to_E0_s": {"mixed": mixed.seconds, "f64": plain.seconds if plain else None, "warm": None},
-        "E0": {"mixed": mixed.E0, "f64": plain.E0 if plain else None,
-               "rel_diff": abs(mixed.E0 - plain.E0) / abs(plain.E0) if plain else None},
-        "products": {"mixed": mixed.iterations, "mixed_f32": mixed.iterations_f32,
-                     "f64": plain.iterations if plain else None},
+        "time_to_E0_s": {"f64": plain.seconds if plain else None, "mixed": mixed.seconds,
+                         "warm": warm_info["seconds_including_network"] if warm_info else None},
+        "E0": {"f64": plain.E0 if plain else None, "mixed": mixed.E0, "warm": warm_r.E0 if warm_r else None,
+               "mixed_rel_diff_vs_f64": abs(mixed.E0 - plain.E0) / abs(plain.E0) if plain else None,
+               "warm_rel_diff_vs_f64": abs(warm_r.E0 - plain.E0) / abs(plain.E0) if (plain and warm_r) else None},
+        "products": {"f64": plain.iterations if plain else None, "mixed": mixed.iterations,
+                     "mixed_f32": mixed.iterations_f32, "warm": warm_r.iterations if warm_r else None},
+        "warm": warm_info,
+        "batched": batched,
         "sigma": sig,
     }
     print(json.dumps(out), flush=True)

@@ -4,7 +4,7 @@
         --out paper_2001_01978_amd/weights/warm_o24_n12.npz --report report.json
 
 Training instances: the random family at fixed (omega, n) with seeds
-[0, train); held-out instances: seeds [10^6, 10^6 + heldout).  Labels are the
+[seed0, seed0 + train); held-out instances: seeds [10^6, 10^6 + heldout).  Labels are the
 half occupations from the batched GPU solver (tol 1e-8).  The report holds
 the training curve and, per held-out instance, the Lanczos products from the
 warm start (with its RANDOM fallback) and from the RANDOM start, both run to
@@ -42,12 +42,23 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--report", required=True)
     ap.add_argument("--labels-cache", default=None, help="npz of (X, T) to reuse instead of solving")
+    ap.add_argument("--family", default="family3", choices=["family3", "large"],
+                    help="family3: G0 ~ U[0.1,0.6); large: G0 = 0.3 (the Omega=32/34 workload family)")
+    ap.add_argument("--train-seed0", type=int, default=0, help="first training seed (training seeds: seed0 .. seed0+train)")
+    ap.add_argument("--single", action="store_true",
+                    help="label with the single-instance mixed-precision solver (spaces beyond the batched kernel)")
     args = ap.parse_args(argv)
 
     import torch
     from . import inputs, pairdiag, warm
 
     om, n = args.omega, args.n
+
+    def instance(seed):
+        if args.family == "large":
+            return inputs.c5_instance(om, n, seed=seed)
+        return inputs.family3_instance(seed, omega=om, n=n)
+
     t0 = time.perf_counter()
     if args.labels_cache and os.path.exists(args.labels_cache):
         d = np.load(args.labels_cache, allow_pickle=False)
@@ -57,16 +68,19 @@ def main(argv=None):
     else:
         Xs, Ts = [], []
         for c0 in range(0, args.train, args.chunk):
-            insts = [inputs.family3_instance(s, omega=om, n=n) for s in range(c0, min(args.train, c0 + args.chunk))]
-            X, T, r = warm.labels(insts, tol=args.label_tol, krylov=args.krylov)
+            insts = [instance(args.train_seed0 + s) for s in range(c0, min(args.train, c0 + args.chunk))]
+            if args.single:
+                X, T = warm.labels_single(insts, tol=args.label_tol, krylov=args.krylov, log=log)
+            else:
+                X, T, r = warm.labels(insts, tol=args.label_tol, krylov=args.krylov)
+                log(f"labels {c0 + len(insts)}/{args.train}: batched kernel {r.info['kernel_seconds']:.1f} s, "
+                    f"{r.converged.sum()}/{len(insts)} converged")
             Xs.append(X)
             Ts.append(T)
-            log(f"labels {c0 + len(insts)}/{args.train}: batched kernel {r.info['kernel_seconds']:.1f} s, "
-                f"{r.converged.sum()}/{len(insts)} converged")
+            if args.labels_cache:
+                np.savez(args.labels_cache, X=np.concatenate(Xs), T=np.concatenate(Ts))
         X, T = np.concatenate(Xs), np.concatenate(Ts)
         label_seconds = time.perf_counter() - t0
-        if args.labels_cache:
-            np.savez(args.labels_cache, X=X, T=T)
 
     t1 = time.perf_counter()
     net = warm.WarmNet(om, hidden=args.hidden, seed=0)
@@ -80,16 +94,23 @@ def main(argv=None):
     basis = pairdiag.Basis(om, n, store_states=False)
     rows = []
     for s in range(10 ** 6, 10 ** 6 + args.heldout):
-        _, _, eps, V = inputs.family3_instance(s, omega=om, n=n)
-        rw = warm.solve(basis, eps, V, net, krylov=args.krylov, tol=args.tol, want_psi=False)
-        rr = warm.solve(basis, eps, V, None, krylov=args.krylov, tol=args.tol, want_psi=False, seed=s)
+        _, _, eps, V = instance(s)
+        prec = "f32" if args.single else "f64"
+        rw = warm.solve(basis, eps, V, net, krylov=args.krylov, tol=args.tol, want_psi=False, precision=prec)
+        rr = warm.solve(basis, eps, V, None, krylov=args.krylov, tol=args.tol, want_psi=False, seed=s,
+                        precision=prec)
         rows.append(dict(seed=s, warm_products=rw.iterations, random_products=rr.iterations,
                          warm_seconds=rw.seconds, random_seconds=rr.seconds, fallback=rw.fallback_used,
                          dE=abs(rw.E0 - rr.E0) / abs(rr.E0), converged=bool(rw.converged and rr.converged)))
-        if len(rows) % 20 == 0:
+        if len(rows) % 20 == 0 or args.single:
             w = np.mean([r["warm_products"] for r in rows])
             rnd = np.mean([r["random_products"] for r in rows])
             log(f"held-out {len(rows)}: mean products warm {w:.1f} vs random {rnd:.1f}")
+    if not rows:
+        with open(args.report, "w") as f:
+            json.dump(dict(omega=om, n=n, train_instances=int(X.shape[0]), epochs=args.epochs, loss_first=hist[0],
+                           loss_last=hist[-1], label_seconds=label_seconds, train_seconds=train_seconds), f, indent=1)
+        return 0
     w = np.array([r["warm_products"] for r in rows])
     rnd = np.array([r["random_products"] for r in rows])
     report = dict(omega=om, n=n, train_instances=int(X.shape[0]), heldout=len(rows), epochs=args.epochs,

@@ -179,4 +179,22 @@ def labels(instances, tol=1e-8, krylov=20):
     return np.stack(X), np.stack(T), r
 
 
+def labels_single(instances, tol=1e-4, krylov=16, precision="f32", log=None):
+    """Half occupations from the single-instance solver (for spaces beyond the
+    batched kernel), canonical orbit order."""
+    X, T = [], []
+    basis = None
+    for q, (om, n, eps, V) in enumerate(instances):
+        if basis is None or (basis.omega, basis.n) != (om, n):
+            basis = pdg.Basis(om, n, store_states=False)
+        r = pdg.lanczos_ground(basis, eps, V, krylov=krylov, tol=tol, start="hf", precision=precision,
+                               want_psi=False)
+        x, perm = features(om, eps, V)
+        X.append(x)
+        T.append((r.occ[perm] / 2.0).astype(np.float32))
+        if log:
+            log(f"label {q + 1}/{len(instances)}: products {r.iterations}, rho {r.residual:.1e}, {r.seconds:.1f} s")
+    return np.stack(X), np.stack(T)
+
+
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
