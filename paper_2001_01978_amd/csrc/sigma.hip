@@ -4,26 +4,30 @@
 
 namespace pd {
 
-hipError_t sigma_r32_f32(int, int, int64_t, const float *, const float *, float, const float *, float *, hipStream_t);
+hipError_t sigma_r32_f32(int, int, int64_t, const float *, const float *, float, const float *, float *, unsigned *,
+                         hipStream_t);
 hipError_t sigma_r32_f64(int, int, int64_t, const double *, const double *, double, const double *, double *,
+                         unsigned *, hipStream_t);
+hipError_t sigma_r64_f32(int, int, int64_t, const float *, const float *, float, const float *, float *, unsigned *,
                          hipStream_t);
-hipError_t sigma_r64_f32(int, int, int64_t, const float *, const float *, float, const float *, float *, hipStream_t);
 hipError_t sigma_r64_f64(int, int, int64_t, const double *, const double *, double, const double *, double *,
-                         hipStream_t);
+                         unsigned *, hipStream_t);
 
 hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd_dtype dt, const void *x, void *y,
                         hipStream_t s, double dsum64, float dsum32) {
     if (dim <= 0) return hipSuccess;
     const bool small = dim < (int64_t(1) << 32);
     const unsigned char *base = reinterpret_cast<const unsigned char *>(coef);  // device address
+    unsigned *sched = reinterpret_cast<unsigned *>(const_cast<unsigned char *>(base) + offsetof(CoefBlock, sched));
     if (dt == PD_F64) {
         const double *d = reinterpret_cast<const double *>(base + offsetof(CoefBlock, d64));
         const double *V = reinterpret_cast<const double *>(base + offsetof(CoefBlock, V64));
-        return (small ? sigma_r32_f64 : sigma_r64_f64)(omega, n, dim, d, V, dsum64, (const double *)x, (double *)y, s);
+        return (small ? sigma_r32_f64 : sigma_r64_f64)(omega, n, dim, d, V, dsum64, (const double *)x, (double *)y, sched,
+                                                     s);
     }
     const float *d = reinterpret_cast<const float *>(base + offsetof(CoefBlock, d32));
     const float *V = reinterpret_cast<const float *>(base + offsetof(CoefBlock, V32));
-    return (small ? sigma_r32_f32 : sigma_r64_f32)(omega, n, dim, d, V, dsum32, (const float *)x, (float *)y, s);
+    return (small ? sigma_r32_f32 : sigma_r64_f32)(omega, n, dim, d, V, dsum32, (const float *)x, (float *)y, sched, s);
 }
 
 }  // namespace pd

@@ -58,6 +58,7 @@ struct Params {
     const T *__restrict__ d;   // omega pair energies
     const T *__restrict__ V;   // omega x omega
     T dsum;                    // sum of d (for the mirrored diagonal)
+    unsigned *sched;           // 9 tile counters, zero on entry and on exit
 };
 
 // Stages the binomial table C(p, k) (p < omega, k < ks), the couplings and the
@@ -165,19 +166,39 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
     __syncthreads();
 
     const int64_t dim = P.dim;
-    // Workgroups are dealt to the 8 XCDs round-robin (workgroup id mod 8).
-    // Each XCD walks its own contiguous eighth of the tiles, so the rows in
-    // flight on one XCD, and the x lines their hops touch, stay together in
-    // that XCD's L2 instead of being spread over all eight.
-    int64_t t_begin = blockIdx.x, t_end = P.ntiles, t_step = gridDim.x;
     if ((gridDim.x & 7) == 0 && P.ntiles >= (int64_t)gridDim.x) {
+        // Workgroups are dealt to the 8 XCDs round-robin (workgroup id mod
+        // 8).  Each XCD owns a contiguous eighth of the tiles and hands them
+        // out in order from its own counter, so the tiles in flight on one
+        // XCD are always the most recently issued ones: a contiguous window
+        // of ranks whose hops share x lines in that XCD's L2.  (A static
+        // stride lets workgroups drift apart over hundreds of tiles and
+        // spreads the window.)
+        __shared__ int64_t s_tile;
+        const int xcd = blockIdx.x & 7;
         const int64_t per_xcd = (P.ntiles + 7) / 8;
-        const int64_t xcd = blockIdx.x & 7;
-        t_begin = xcd * per_xcd + (blockIdx.x >> 3);
-        t_end = (xcd + 1) * per_xcd < P.ntiles ? (xcd + 1) * per_xcd : P.ntiles;
-        t_step = gridDim.x >> 3;
+        const int64_t lo = xcd * per_xcd;
+        const int64_t hi = lo + per_xcd < P.ntiles ? lo + per_xcd : P.ntiles;
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = lo + (int64_t)atomicAdd(&P.sched[xcd], 1u);
+            __syncthreads();
+            const int64_t tile = s_tile;
+            __syncthreads();
+            if (tile >= hi) break;
+            const int64_t row = tile * kThreads + threadIdx.x;
+            if (row < dim) P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x);
+        }
+        // The last workgroup to finish clears the counters for the next launch.
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (atomicAdd(&P.sched[8], 1u) == gridDim.x - 1) {
+                for (int i = 0; i < 9; ++i) atomicExch(&P.sched[i], 0u);
+                __threadfence();
+            }
+        }
+        return;
     }
-    for (int64_t tile = t_begin; tile < t_end; tile += t_step) {
+    for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
         const int64_t row = tile * kThreads + threadIdx.x;
         if (row >= dim) continue;
         P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x);
@@ -210,7 +231,7 @@ hipError_t dispatch_nn(const Params<R, T> &P, hipStream_t stream) {
 // y = H x with rank type R and value type T.
 template <typename R, typename T>
 hipError_t launch_typed(int omega, int n, int64_t dim, const T *d, const T *V, T dsum, const T *x, T *y,
-                        hipStream_t stream) {
+                        unsigned *sched, hipStream_t stream) {
     Params<R, T> P;
     const bool comp = n > omega - n;
     P.omega = omega;
@@ -223,6 +244,7 @@ hipError_t launch_typed(int omega, int n, int64_t dim, const T *d, const T *V, T
     P.d = d;
     P.V = V;
     P.dsum = dsum;
+    P.sched = sched;
     return comp ? dispatch_nn<R, T, true>(P, stream) : dispatch_nn<R, T, false>(P, stream);
 }
 

@@ -3,7 +3,7 @@
 
 namespace pd {
 hipError_t sigma_r32_f64(int omega, int n, int64_t dim, const double *d, const double *V, double dsum, const double *x,
-                        double *y, hipStream_t s) {
-    return sigma_detail::launch_typed<uint32_t, double>(omega, n, dim, d, V, dsum, x, y, s);
+                        double *y, unsigned *sched, hipStream_t s) {
+    return sigma_detail::launch_typed<uint32_t, double>(omega, n, dim, d, V, dsum, x, y, sched, s);
 }
 }  // namespace pd

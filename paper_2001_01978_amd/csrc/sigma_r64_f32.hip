@@ -3,7 +3,7 @@
 
 namespace pd {
 hipError_t sigma_r64_f32(int omega, int n, int64_t dim, const float *d, const float *V, float dsum, const float *x,
-                        float *y, hipStream_t s) {
-    return sigma_detail::launch_typed<uint64_t, float>(omega, n, dim, d, V, dsum, x, y, s);
+                        float *y, unsigned *sched, hipStream_t s) {
+    return sigma_detail::launch_typed<uint64_t, float>(omega, n, dim, d, V, dsum, x, y, sched, s);
 }
 }  // namespace pd

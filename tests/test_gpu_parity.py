@@ -126,6 +126,22 @@ def test_sigma_random_f64_and_f32(torch_cuda, pdg, oracle_mod, om, n):
     assert np.all(np.abs(y32 - want32) <= (2 * K + 4) * 2.0 ** -24 * absx)
 
 
+def test_sigma_repeated_launches_cover_every_row(torch_cuda, pdg, oracle_mod):
+    """Omega=24, n=12 (10,563 tiles: the per-XCD tile counters are used): every
+    launch writes every row, whatever ran before on the same basis."""
+    torch = torch_cuda
+    om, n, eps, V = inputs.dyadic_instance(24, 12, seed=77)
+    d = math.comb(om, n)
+    x = inputs.dyadic_vector(om + n, d, bits=6)
+    want = oracle_mod.sigma(om, n, eps, V, oracle_mod.basis_alg1(om, n), x)
+    b = pdg.Basis(om, n, store_states=False)
+    for dt in (torch.float64, torch.float32, torch.float32, torch.float64):
+        xt = torch.tensor(x, dtype=dt, device="cuda")
+        y = torch.full_like(xt, float("nan"))
+        b.sigma(eps, V, xt, y)
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), want), dt
+
+
 def test_sigma_matches_paper_6x6(torch_cuda, pdg, oracle_mod, golden_dir):
     import json, os
     torch = torch_cuda
