@@ -11,8 +11,9 @@ else) to an FP64-checked residual of 1e-10, from a seeded random start.
 value = sigma non-zeros generated per second of the timed solves (whole job).
 Also reported: time-to-E0 for plain FP64, mixed precision and the learned
 warm start (mixed precision from the network's product-state start), per-
-product sigma rates, the roofline of the dominant kernel (the FP32 sigma)
-from its HIP-event durations inside the timed region, the batched solver on
+product sigma rates, the roofline of the dominant kernel (the FP32 sigma:
+VALU-issue bound; its gather-model and measured HBM rates alongside) from
+its HIP-event durations inside the timed region, the batched solver on
 4096 instances of the uneven random family, and the oracle's CPU rate on a
 bounded sample of rows of the same instance.
 """
@@ -27,6 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# 32-bit VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one wave64 instruction per SIMD every 4 cycles; FP32 FMA counted as one op).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic VALU work per non-zero of the prefix-delta sigma: target rank =
+# rank + A + B (2 adds), up/down choice (compare + select), gather address,
+# coefficient address, FMA.
+OPS_PER_NONZERO = 7
 
 
 def parse():
@@ -195,7 +203,8 @@ def main():
     s32 = sum(r.sigma_seconds_f32 for r in results)
     avg32 = s32 / max(n32, 1)
     balg32 = D * (K * 4 + 8)
-    achieved = balg32 / avg32 / 1e9 if n32 else None
+    ops32 = D * K * OPS_PER_NONZERO
+    achieved = ops32 / avg32 / 1e12 if n32 else None
 
     plain = None
     if not args.no_plain:
@@ -263,12 +272,19 @@ def main():
         "config": {"workload": f"ground state, Omega={om}, n={n}, dim={D}, mixed precision, "
                                f"krylov={args.krylov}, tol={args.tol:g}",
                    "omega": om, "n": n, "dim": D, "hops_per_row": K, "krylov": args.krylov},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Top/s",
+                     "frac": (achieved / PEAK_VALU_TOPS) if achieved else None,
                      "traffic": traffic,
                      "kernel": "sigma_kernel<uint32,float,16>",
-                     "algorithmic_bytes_per_launch": balg32,
-                     "avg_launch_ms": avg32 * 1e3},
+                     "ops_per_nonzero": OPS_PER_NONZERO,
+                     "algorithmic_ops_per_launch": ops32,
+                     "avg_launch_ms": avg32 * 1e3,
+                     "hbm": {"gather_model_bytes_per_launch": balg32,
+                             "gather_model_GBps": balg32 / avg32 / 1e9 if n32 else None,
+                             "measured_GBps": traffic / avg32 / 1e9 if (traffic and n32) else None,
+                             "measured_frac_of_peak": traffic / avg32 / 1e9 / PEAK_HBM_GBS
+                             if (traffic and n32) else None,
+                             "peak_GBps": PEAK_HBM_GBS}},
         "cpu_baseline": cpu,
         "time_to_E0_s": {"f64": plain.seconds if plain else None, "mixed": mixed.seconds,
                          "warm": warm_info["seconds_including_network"] if warm_info else None},

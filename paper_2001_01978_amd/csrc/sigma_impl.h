@@ -18,15 +18,19 @@
 //     with S_c(q) = sum over occupied p_j > q of C(p_j, j + c) (c = 0, -1, +1)
 //     and t = number of occupied orbits below b;
 //   * rank + A for every occupied orbit sits in registers (the pair count NN
-//     is a template parameter, so the loops unroll completely); the lane then
-//     walks the orbits from the top, updating the suffix sums, and at every
-//     empty orbit b computes all NN targets, issues all NN gathers, then
-//     accumulates -- NN loads in flight per lane.
+//     is a template parameter, so the loops unroll completely), and the
+//     suffix-sum differences that B needs, one pair per count of occupied
+//     orbits above b, sit in the lane's slots of an LDS array; the lane then
+//     takes its own omega - NN empty orbits from the top and, for each, reads
+//     its pair of differences, computes all NN targets, issues all NN
+//     gathers, then accumulates -- NN loads in flight per lane.  Every lane
+//     runs the same number of hop blocks, so the occupation pattern causes no
+//     divergence.
 //
 // Lanes of a wave hold consecutive ranks, which share their high orbits.
-// Walking and numbering orbits from the top makes every lane do the same
-// physical hop at the same time on those shared orbits, so those gathers hit
-// consecutive addresses.
+// Numbering orbits from the top makes every lane do the same physical hop at
+// the same time on those shared orbits, so those gathers hit consecutive
+// addresses.
 //
 // When n > omega - n the kernel works in the complementary space (holes as
 // particles, COMP): the state ~s of rank dim-1-k has omega-n pairs, a hop O->E
@@ -43,7 +47,7 @@
 namespace pd {
 namespace sigma_detail {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int64_t kMaxGrid = 256 * 16;
 
 template <typename R, typename T>
@@ -83,9 +87,11 @@ __host__ __device__ inline size_t table_bytes(int omega, int ks) {
     return (((size_t)omega * ks * sizeof(R) + 15) & ~size_t(15)) + ((size_t)omega * omega + omega) * sizeof(T);
 }
 
-// (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
+// (H x)[row] for one row, walking all orbits from the top and updating the
+// suffix sums in registers (no LDS scratch; lanes diverge on the occupation
+// pattern).  Used where LDS is scarce (the batched solver's workgroups).
 template <typename R, typename T, int NN, bool COMP>
-__device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
+__device__ __forceinline__ T sigma_row_walk(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
                                        const T *ds, T dsum, const T *__restrict__ x) {
     const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
 
@@ -156,6 +162,106 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     return acc;
 }
 
+// Per-lane LDS scratch of sigma_row: 2 (NN + 1) rank words per thread.
+template <typename R>
+__host__ __device__ inline size_t prefix_bytes(int nn) {
+    return (size_t)(2 * nn + 2) * kThreads * sizeof(R);
+}
+
+// (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
+// pre: this workgroup's prefix area (prefix_bytes); the lane uses entries
+// [i * kThreads + threadIdx.x] only.
+template <typename R, typename T, int NN, bool COMP>
+__device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
+                                       const T *ds, T dsum, const T *__restrict__ x, R *pre) {
+    const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
+
+    // state of rank rk: greedy, orbits from the top
+    uint64_t s = 0;
+    {
+        R rem = rk;
+        int k = NN;
+        for (int p = omega - 1; p >= 0 && k > 0; --p) {
+            R c = Ct[p * ks + k];
+            if (c <= rem) {
+                s |= 1ull << p;
+                rem -= c;
+                --k;
+            }
+        }
+    }
+
+    // Occupied orbits numbered from the top (r = 0 highest).  rup/rdn: rank
+    // plus the removed-orbit term of an up / down hop.  The suffix-sum
+    // differences seen by an empty orbit with A occupied orbits above it,
+    //   D0[A] = S_0 - S_m  and  D1[A] = S_p - S_0  (sums over those A orbits),
+    // go to the lane's LDS slots, where each empty orbit reads its own A.
+    R rup[NN > 0 ? NN : 1], rdn[NN > 0 ? NN : 1];
+    int apos[NN > 0 ? NN : 1];
+    T dacc = T(0);
+    const int lane = threadIdx.x;
+    {
+        uint64_t occ = s;
+        R s0 = 0, sm = 0, sp = 0;
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+            const int a = 63 - __clzll((long long)occ);
+            occ &= ~(1ull << a);
+            const int j = NN - r;
+            const R c0 = Ct[a * ks + j], cm = Ct[a * ks + j - 1], cp = Ct[a * ks + j + 1];
+            pre[r * kThreads + lane] = s0 - sm;
+            pre[(NN + 1 + r) * kThreads + lane] = sp - s0;
+            rup[r] = rk + (sm - s0 - c0);
+            rdn[r] = rk + (s0 - sp - cp);
+            apos[r] = a;
+            s0 += c0;
+            sm += cm;
+            sp += cp;
+            dacc += ds[a];
+        }
+        pre[NN * kThreads + lane] = s0 - sm;
+        pre[(2 * NN + 1) * kThreads + lane] = sp - s0;
+    }
+    // Mirrored space: element dim - 1 - rank; fold the mirror into rup/rdn.
+    if (COMP) {
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+            rup[r] = (R)(dim - 1) - rup[r];
+            rdn[r] = (R)(dim - 1) - rdn[r];
+        }
+    }
+
+    T acc = (COMP ? (dsum - dacc) : dacc) * x[row];
+    if (NN == 0) return acc;
+    // Every lane walks its own omega - NN empty orbits from the top, so all
+    // lanes run the same number of hop blocks (no divergence on the
+    // occupation pattern).  The e-th empty orbit b has A = (omega-1-b) - e
+    // occupied orbits above it.
+    const uint64_t full = omega >= 64 ? ~0ull : ((1ull << omega) - 1);
+    uint64_t E = ~s & full;
+    const int ne = omega - NN;
+    for (int e = 0; e < ne; ++e) {
+        const int b = 63 - __clzll((long long)E);
+        E &= ~(1ull << b);
+        const int A = (omega - 1 - b) - e;
+        const int t = NN - A;
+        const R bup = pre[A * kThreads + lane] + Ct[b * ks + t];
+        const R bdn = pre[(NN + 1 + A) * kThreads + lane] + Ct[b * ks + t + 1];
+        const T *Vrow = Vs + b * omega;
+        T xv[NN > 0 ? NN : 1];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+            // r < A: a_r above b (down hop); otherwise below (up hop)
+            const R jt = COMP ? ((r < A) ? (R)(rdn[r] - bdn) : (R)(rup[r] - bup))
+                              : ((r < A) ? (R)(rdn[r] + bdn) : (R)(rup[r] + bup));
+            xv[r] = x[(int64_t)jt];
+        }
+#pragma unroll
+        for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
+    }
+    return acc;
+}
+
 template <typename R, typename T, int NN, bool COMP>
 __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -163,6 +269,7 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
     R *Ct;
     T *Vs, *ds;
     stage_tables<R, T>(smem, omega, ks, P.V, P.d, Ct, Vs, ds);
+    R *pre = reinterpret_cast<R *>(smem + ((table_bytes<R, T>(omega, ks) + 15) & ~size_t(15)));
     __syncthreads();
 
     const int64_t dim = P.dim;
@@ -186,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
             __syncthreads();
             if (tile >= hi) break;
             const int64_t row = tile * kThreads + threadIdx.x;
-            if (row < dim) P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x);
+            if (row < dim) P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre);
         }
         // The last workgroup to finish clears the counters for the next launch.
         if (threadIdx.x == 0) {
@@ -201,13 +308,23 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
     for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
         const int64_t row = tile * kThreads + threadIdx.x;
         if (row >= dim) continue;
-        P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x);
+        P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre);
     }
 }
 
 template <typename R, typename T, int NN, bool COMP>
 hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
-    const size_t smem = table_bytes<R, T>(P.omega, P.ks);
+    const size_t smem = ((table_bytes<R, T>(P.omega, P.ks) + 15) & ~size_t(15)) + prefix_bytes<R>(NN);
+    // Large pair counts with 64-bit ranks need more than the default 64 KB.
+    if (smem > 64 * 1024) {
+        static bool raised = false;
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+            raised = true;
+        }
+    }
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
     if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
     hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP>), dim3((unsigned)grid), dim3(kThreads), smem, stream, P);
