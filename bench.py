@@ -293,6 +293,9 @@ def main():
                "warm_rel_diff_vs_f64": abs(warm_r.E0 - plain.E0) / abs(plain.E0) if (plain and warm_r) else None},
         "products": {"f64": plain.iterations if plain else None, "mixed": mixed.iterations,
                      "mixed_f32": mixed.iterations_f32, "warm": warm_r.iterations if warm_r else None},
+        "reorth_second_passes": {"f64": plain.reorth_second_passes if plain else None,
+                                 "mixed": mixed.reorth_second_passes,
+                                 "warm": warm_r.reorth_second_passes if warm_r else None},
         "warm": warm_info,
         "batched": batched,
         "sigma": sig,

@@ -110,7 +110,8 @@ pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
 /* ------------------------------------------------------------------ Lanczos
  * Restarted, fully reorthogonalised Lanczos (Sec. 3.4, Alg. lanczos): Krylov
  * vectors are orthogonalised against all stored vectors (classical
- * Gram-Schmidt applied twice), the lowest Ritz pair of the krylov x krylov
+ * Gram-Schmidt, applied a second time when the first pass cancels more than
+ * 127/128 of the norm), the lowest Ritz pair of the krylov x krylov
  * tridiagonal matrix comes from Sturm bisection and inverse iteration, and
  * the iteration restarts from the
  * ground-state Ritz vector.  Convergence (Eq. convergence): the restarted
@@ -144,6 +145,7 @@ typedef struct {
     double sigma_seconds_f64;  /* summed device time of the FP64 products (HIP events) */
     double sigma_seconds_f32;  /* summed device time of the FP32 products (HIP events) */
     int fallback_used;         /* 1 if the fallback replaced the caller's start vector */
+    int reorth_second_passes;  /* steps whose Gram-Schmidt needed the second pass */
 } pd_lanczos_info;
 
 void pd_lanczos_default_opts(pd_lanczos_opts *o);

@@ -1,10 +1,24 @@
 // Restarted, fully reorthogonalised Lanczos driver (Sec. 3.4, Alg. lanczos).
 //
 // One cycle builds up to m = krylov orthonormal vectors q_1..q_m in the
-// workspace.  Step k: p = H q_k; c = Q^T p (so alpha_k = c_k); p -= Q c;
-// c' = Q^T p; p -= Q c' (Gram-Schmidt against every stored vector, applied
-// twice; this also removes alpha_k q_k and beta_{k-1} q_{k-1}); beta_k = ||p||;
-// q_{k+1} = p / beta_k.  After the cycle the lowest Ritz pair of the
+// workspace.  Step k, three streaming passes at most:
+//   1. ps = H q_k - sigma_k q_k - beta_{k-1} q_{k-1} on the fly, with sigma_k =
+//      alpha_{k-1} (on the first step of a cycle: the Ritz value of the
+//      previous cycle, 0 at the start, and no beta term): the recurrence of
+//      Alg. lanczos with the estimate sigma_k in place of alpha_k; c = Q^T ps,
+//      ||ps|| and ||H q_k||;
+//   2. v = ps - Q c (Gram-Schmidt against every stored vector, which also
+//      corrects alpha_k = sigma_k + c_k), with c' = Q^T v and ||v||;
+//   3. v -= Q c' only when ||v|| < ||ps|| / sqrt(2) or ||v|| < ||H q_k|| / 128.
+// A classical pass multiplies the orthogonality error already in Q by
+// ||c|| / ||v|| and adds rounding of order u ||H q_k|| / ||v||; the first test
+// (Daniel, Gragg, Kaufman and Stewart) keeps the factor <= 1, the second keeps
+// the rounding below 128 u.  Subtracting the recurrence first makes c small,
+// so the tests pass on most steps (without it c is dominated by alpha_k and
+// the second pass is always needed).  beta_k = ||v||; q_{k+1} = v / beta_k is
+// stored as v with the scale 1/beta_k, so no pass normalises it, and pass 2
+// (or 3) also writes the FP32 copy for the next product.  The last step of a
+// cycle needs only alpha_m.  After the cycle the lowest Ritz pair of the
 // tridiagonal L = tridiag(beta, alpha, beta) gives psi = Q y, the start of the
 // next cycle.  The first step of every cycle measures the residual of its
 // start vector, |beta_1 / alpha_1| = ||H q - (q^T H q) q|| / |q^T H q|
@@ -34,8 +48,11 @@ struct Layout {
     int m = 0;
 };
 
-constexpr int kScalars = 512;  // doubles: c[64], c2[64], nrm2, sum, occ[64]
-constexpr int kOffC = 0, kOffC2 = 64, kOffNrm = 192, kOffSum = 193, kOffOcc = 256;
+constexpr int kScalars = 512;  // doubles: c[66], c2[65], nrm2, sum, occ[64]
+constexpr int kOffC = 0, kOffC2 = 80, kOffNrm = 192, kOffSum = 193, kOffOcc = 256;
+// Thresholds of the second Gram-Schmidt pass (see the step description above).
+constexpr double kReorthEta = 0.70710678118654752;   // 1/sqrt(2)
+constexpr double kReorthTau = 1.0 / 128.0;
 
 Layout layout_for(int64_t dim, int krylov, int precision) {
     Layout L;
@@ -180,7 +197,8 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             }
             PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, q, p, s, dsum64, dsum32));
             ++info.iterations;
-            PD_HIP(launch_gemvt(q, ld, 1, dim, p, partials, scal + kOffC, s));
+            const double one = 1.0, zero = 0.0;
+            PD_HIP(launch_project(q, ld, 1, dim, p, false, 1.0, &one, &zero, partials, scal + kOffC, s));
             PD_HIP(dev.fetch(kOffC, 1));
             rq[t] = dev.host[kOffC];
         }
@@ -201,38 +219,73 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
     PD_HIP(hipEventCreate(&ev.a));
     PD_HIP(hipEventCreate(&ev.b));
 
-    std::vector<double> alpha(m), beta(m), y(m);
+    std::vector<double> alpha(m), beta(m), y(m), yy(m);
+    // Column scales: q_j = sc[j] * (stored column j).  Columns are written
+    // unnormalised by the Gram-Schmidt pass itself; 1/beta is kept here.
+    std::vector<double> sc(m + 1, 1.0);
+    // Part of the three-term recurrence subtracted before the projection:
+    // sigma_k q_k + beta_{k-1} q_{k-1}, with sigma_k = alpha_{k-1} (the Ritz
+    // value of the previous cycle at k = 0), as coefficients of stored columns.
+    std::vector<double> d(m, 0.0);
     double theta = 0.0, residual = INFINITY, e0 = NAN;
     bool converged = false;
     bool final_check = false;  // this cycle only measures its start vector
     int cycle = 0;
     for (cycle = 0;; ++cycle) {
         int m_eff = m;
+        sc[0] = 1.0;
         for (int k = 0; k < m; ++k) {
             double *qk = Q + (size_t)k * ld;
             const bool f32_step = x32 && k >= 1;
+            // the product of the stored column k (its FP32 copy for FP32 steps); H q_k = sc[k] * it
+            const void *pin = f32_step ? static_cast<const void *>(y32) : static_cast<const void *>(p);
             PD_HIP(hipEventRecord(ev.a, s));
             if (f32_step) {
                 PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, x32, y32, s, dsum64, dsum32));
-                PD_HIP(hipEventRecord(ev.b, s));
-                PD_HIP(launch_f32_to_f64(y32, dim, p, s));
                 ++info.iterations_f32;
             } else {
                 PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32));
-                PD_HIP(hipEventRecord(ev.b, s));
             }
+            PD_HIP(hipEventRecord(ev.b, s));
             ++info.iterations;
-            PD_HIP(launch_gemvt(Q, ld, k + 1, dim, p, partials, scal + kOffC, s));
-            PD_HIP(launch_update_gemvt(Q, ld, k + 1, dim, scal + kOffC, p, p, partials, scal + kOffC2, s));
-            PD_HIP(launch_update_norm(Q, ld, k + 1, dim, scal + kOffC2, p, p, partials, scal + kOffNrm, s));
-            PD_HIP(dev.fetch2(kOffC + k, 1, kOffNrm, 1));
+            const double sp = sc[k];
+            const double sigma = k > 0 ? alpha[k - 1] : theta;
+            std::fill(d.begin(), d.begin() + k + 1, 0.0);
+            d[k] = sigma * sc[k];
+            if (k > 0) d[k - 1] = beta[k - 1] * sc[k - 1];
+            // ps = H q_k - sigma q_k - beta_{k-1} q_{k-1}; c = Q^T ps (alpha_k = sigma + c_k),
+            // ||ps||^2 and ||H q_k||^2
+            PD_HIP(launch_project(Q, ld, k + 1, dim, pin, f32_step, sp, sc.data(), d.data(), partials,
+                                  scal + kOffC, s));
+            const bool store = k + 1 < m;      // q_{k+1} is needed (else only alpha_k, and beta_0 at k = 0)
+            double nrm_v = 0.0;
+            if (store || k == 0) {
+                // v = H q_k - Q c, written as the next stored column (or into w), with c' = Q^T v, ||v||^2
+                double *dst = store ? Q + (size_t)(k + 1) * ld : w;
+                float *dst32 = store ? x32 : nullptr;
+                PD_HIP(launch_update_project(Q, ld, k + 1, dim, scal + kOffC, sc.data(), d.data(), pin, f32_step,
+                                             sp, dst, dst32, partials, scal + kOffC2, s));
+                PD_HIP(dev.fetch2(kOffC + k, 3, kOffC2 + k + 1, 1));
+                nrm_v = dev.host[kOffC2 + k + 1];
+                const double nrm_ps = dev.host[kOffC + k + 1], nrm_hq = dev.host[kOffC + k + 2];
+                if (!(nrm_v >= kReorthEta * kReorthEta * nrm_ps && nrm_v >= kReorthTau * kReorthTau * nrm_hq)) {
+                    // large cancellation: Gram-Schmidt once more, v -= Q c'
+                    PD_HIP(launch_update_norm(Q, ld, k + 1, dim, scal + kOffC2, sc.data(), dst, dst32, partials,
+                                              scal + kOffNrm, s));
+                    PD_HIP(dev.fetch(kOffNrm, 1));
+                    nrm_v = dev.host[kOffNrm];
+                    ++info.reorth_second_passes;
+                }
+            } else {
+                PD_HIP(dev.fetch(kOffC + k, 1));
+            }
             {
                 float ms = 0.0f;
                 PD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
                 (f32_step ? info.sigma_seconds_f32 : info.sigma_seconds_f64) += 1e-3 * ms;
             }
-            alpha[k] = dev.host[kOffC + k];
-            beta[k] = std::sqrt(std::max(dev.host[kOffNrm], 0.0));
+            alpha[k] = sigma + dev.host[kOffC + k];
+            beta[k] = std::sqrt(std::max(nrm_v, 0.0));
             if (k == 0) {
                 e0 = alpha[0];
                 residual = beta[0] / std::max(std::fabs(alpha[0]), 1e-3 * dscale);
@@ -242,20 +295,20 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
                 if (residual <= o->tol) converged = true;
                 if (converged || final_check) break;
             }
+            if (!store) break;
             double tnorm = 0.0;
             for (int i = 0; i <= k; ++i) tnorm = std::max(tnorm, std::fabs(alpha[i]) + beta[i]);
             if (beta[k] <= 1e-14 * std::max(tnorm, 1e-300)) {
                 m_eff = k + 1;  // invariant subspace: the Ritz pair is exact
                 break;
             }
-            if (k + 1 < m) {
-                PD_HIP(launch_scale(p, dim, 1.0 / beta[k], Q + (size_t)(k + 1) * ld, x32, s));
-            }
+            sc[k + 1] = 1.0 / beta[k];
         }
         if (converged || final_check) break;
         if (tridiag_lowest(m_eff, alpha.data(), beta.data(), &theta, y.data()) != 0)
             return fail(PD_EDEVICE, "tridiagonal eigensolver failed (m=%d)", m_eff);
-        PD_HIP(launch_combine(Q, ld, m_eff, dim, y.data(), w, partials, scal + kOffNrm, scal + kOffSum, s));
+        for (int j = 0; j < m_eff; ++j) yy[j] = y[j] * sc[j];
+        PD_HIP(launch_combine(Q, ld, m_eff, dim, yy.data(), w, partials, scal + kOffNrm, scal + kOffSum, s));
         PD_HIP(dev.fetch(kOffNrm, 1));
         double nr = std::sqrt(dev.host[kOffNrm]);
         if (!(nr > 0.0)) return fail(PD_EDEVICE, "Ritz vector vanished");

@@ -101,17 +101,23 @@ hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd
 // dimension ld (elements).  `partials` is scratch of partial_doubles() doubles.
 int vec_grid();
 size_t partial_doubles();
-// c[j] = sum_i Q[j][i] * p[i], j < ncols; result to c_dev (device doubles).
-hipError_t launch_gemvt(const double *Q, int64_t ld, int ncols, int64_t dim, const double *p,
-                        double *partials, double *c_dev, hipStream_t s);
-// pout = pin - Q c (j < ncols); then c2 = Q^T pout.  pin may equal pout.
-hipError_t launch_update_gemvt(const double *Q, int64_t ld, int ncols, int64_t dim,
-                               const double *c, const double *pin, double *pout,
-                               double *partials, double *c2_dev, hipStream_t s);
-// pout = pin - Q c; nrm2_dev[0] = ||pout||^2.
-hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim,
-                              const double *c, const double *pin, double *pout,
-                              double *partials, double *nrm2_dev, hipStream_t s);
+// Krylov columns are stored unnormalised: q_j = sc_j * Qt_j, sc_host[j] on the
+// host.  p is FP32 (p_f32) or FP64 and stands for pf = sp * p; d_host[j] are
+// coefficients of stored columns subtracted first: ps = pf - sum_j d_j Qt_j.
+// out_dev[j] = q_j^T ps (j < ncols), out_dev[ncols] = ||ps||^2,
+// out_dev[ncols + 1] = ||pf||^2.
+hipError_t launch_project(const double *Q, int64_t ld, int ncols, int64_t dim, const void *p, bool p_f32, double sp,
+                          const double *sc_host, const double *d_host, double *partials, double *out_dev,
+                          hipStream_t s);
+// v = sp p - sum_j (d_j + c_dev[j] sc_j) Qt_j  ->  out (FP64) and out32 (FP32
+// copy, may be null); out_dev[j] = q_j^T v (j < ncols), out_dev[ncols] = ||v||^2.
+hipError_t launch_update_project(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
+                                 const double *sc_host, const double *d_host, const void *p, bool p_f32, double sp,
+                                 double *out, float *out32, double *partials, double *out_dev, hipStream_t s);
+// v -= sum_j c_dev[j] q_j in place (and out32); nrm2_dev[0] = ||v||^2.
+hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
+                              const double *sc_host, double *v, float *out32, double *partials, double *nrm2_dev,
+                              hipStream_t s);
 // Up to 64 doubles passed to a kernel by value.
 struct SmallVec {
     double v[64];

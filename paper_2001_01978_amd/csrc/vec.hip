@@ -41,6 +41,35 @@ __device__ __forceinline__ void block_partials(const double (&acc)[KMAX], int nc
     }
 }
 
+// As block_partials for acc[0..ncols), plus extra[0..NX) reduced to partials
+// rows ncols .. ncols + NX - 1.
+template <int KMAX, int NX>
+__device__ __forceinline__ void block_partials_extra(const double (&acc)[KMAX], const double (&extra)[NX],
+                                                     int ncols, double *sh, double *__restrict__ partials) {
+    constexpr int W = KMAX + NX;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        if (j < ncols) {
+            double v = wave_sum(acc[j]);
+            if (lane == 0) sh[wid * W + j] = v;
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+        double v = wave_sum(extra[x]);
+        if (lane == 0) sh[wid * W + KMAX + x] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ncols + NX) {
+        const int j = (int)threadIdx.x < ncols ? (int)threadIdx.x : KMAX + ((int)threadIdx.x - ncols);
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += sh[w * W + j];
+        partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
 // out[j] = scale * sum_b partials[j*nb + b]; one block per column.
 __global__ __launch_bounds__(kThreads) void finalize_kernel(const double *__restrict__ partials, int nb,
                                                             double scale, double *__restrict__ out) {
@@ -58,70 +87,99 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double *__rest
     }
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(kThreads) void gemvt_kernel(const double *__restrict__ Q, int64_t ld, int ncols,
-                                                         int64_t dim, const double *__restrict__ p,
-                                                         double *__restrict__ partials) {
-    __shared__ double sh[kWaves * KMAX];
-    double acc[KMAX];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
-        const double pi = p[i];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < ncols) acc[j] += Q[(size_t)j * ld + i] * pi;
-    }
-    block_partials<KMAX>(acc, ncols, sh, partials);
-}
+// The Krylov columns are stored unnormalised: q_j = sc_j * Qt_j (sc on the
+// host, passed by value).  Columns j >= ncols are never read: every thread
+// loads KMAX columns at index min(j, ncols - 1), so all loads of an element
+// are issued together, and the duplicates get coefficient 0 (their dot
+// products are discarded).
 
-template <int KMAX>
-__global__ __launch_bounds__(kThreads) void update_gemvt_kernel(const double *__restrict__ Q, int64_t ld,
-                                                                int ncols, int64_t dim,
-                                                                const double *__restrict__ c,
-                                                                const double *pin, double *pout,
-                                                                double *__restrict__ partials) {
-    __shared__ double sh[kWaves * KMAX];
-    double cj[KMAX], acc[KMAX];
+// With pf = sp * p and ps = pf - sum_j d_j Qt_j (d: the part of the
+// three-term recurrence known in advance), partials: raw_j = sum_i Qt_j[i]
+// ps[i] (j < ncols), sum_i ps[i]^2 (row ncols), sum_i pf[i]^2 (row ncols + 1).
+template <int KMAX, typename TIn>
+__global__ __launch_bounds__(kThreads) void project_kernel(const double *__restrict__ Q, int64_t ld, int ncols,
+                                                           int64_t dim, const TIn *__restrict__ p, double sp,
+                                                           SmallVec d, double *__restrict__ partials) {
+    __shared__ double sh[kWaves * (KMAX + 2)];
+    double acc[KMAX], dj[KMAX], nrm[2] = {0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
-        cj[j] = (j < ncols) ? c[j] : 0.0;
+        acc[j] = 0.0;
+        dj[j] = (j < ncols) ? d.v[j] : 0.0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
+        const double pf = sp * (double)p[i];
+        double q[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
+        double ps = pf;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) ps -= q[j] * dj[j];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) acc[j] += q[j] * ps;
+        nrm[0] += ps * ps;
+        nrm[1] += pf * pf;
+    }
+    block_partials_extra<KMAX, 2>(acc, nrm, ncols, sh, partials);
+}
+
+// v = sp * p - sum_j (d_j + c_j sc_j) Qt_j  ->  out (and out32); partials:
+// raw sum_i Qt_j[i] v[i] (j < ncols) and sum_i v[i]^2 (row ncols).  c: device.
+template <int KMAX, typename TIn>
+__global__ __launch_bounds__(kThreads) void update_project_kernel(const double *__restrict__ Q, int64_t ld,
+                                                                  int ncols, int64_t dim,
+                                                                  const double *__restrict__ c, SmallVec sc,
+                                                                  SmallVec d, const TIn *__restrict__ p,
+                                                                  double sp, double *__restrict__ out,
+                                                                  float *__restrict__ out32,
+                                                                  double *__restrict__ partials) {
+    __shared__ double sh[kWaves * (KMAX + 1)];
+    double cj[KMAX], acc[KMAX], nrm[1] = {0.0};
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        cj[j] = (j < ncols) ? d.v[j] + c[j] * sc.v[j] : 0.0;
         acc[j] = 0.0;
     }
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
         double q[KMAX];
-        double v = pin[i];
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j) {
-            q[j] = (j < ncols) ? Q[(size_t)j * ld + i] : 0.0;
-            v -= q[j] * cj[j];
-        }
-        pout[i] = v;
+        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
+        double v = sp * (double)p[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) v -= q[j] * cj[j];
+        out[i] = v;
+        if (out32) out32[i] = (float)v;
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) acc[j] += q[j] * v;
+        nrm[0] += v * v;
     }
-    block_partials<KMAX>(acc, ncols, sh, partials);
+    block_partials_extra<KMAX, 1>(acc, nrm, ncols, sh, partials);
 }
 
+// v -= sum_j (c_j sc_j) Qt_j in place (and out32); partials: sum_i v[i]^2.
 template <int KMAX>
 __global__ __launch_bounds__(kThreads) void update_norm_kernel(const double *__restrict__ Q, int64_t ld,
                                                                int ncols, int64_t dim,
-                                                               const double *__restrict__ c, const double *pin,
-                                                               double *pout, double *__restrict__ partials) {
+                                                               const double *__restrict__ c, SmallVec sc,
+                                                               double *v_io, float *__restrict__ out32,
+                                                               double *__restrict__ partials) {
     __shared__ double sh[kWaves * 1];
     double cj[KMAX];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) cj[j] = (j < ncols) ? c[j] : 0.0;
+    for (int j = 0; j < KMAX; ++j) cj[j] = (j < ncols) ? c[j] * sc.v[j] : 0.0;
     double acc[1] = {0.0};
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
-        double v = pin[i];
+        double q[KMAX];
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < ncols) v -= Q[(size_t)j * ld + i] * cj[j];
-        pout[i] = v;
+        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
+        double v = v_io[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) v -= q[j] * cj[j];
+        v_io[i] = v;
+        if (out32) out32[i] = (float)v;
         acc[0] += v * v;
     }
     block_partials<1>(acc, 1, sh, partials);
@@ -138,10 +196,12 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const double *__restr
     double acc[2] = {0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
+        double q[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
         double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < ncols) v += Q[(size_t)j * ld + i] * yj[j];
+        for (int j = 0; j < KMAX; ++j) v += q[j] * yj[j];
         out[i] = v;
         acc[0] += v * v;
         acc[1] += v;
@@ -239,6 +299,27 @@ inline unsigned grid_for(int64_t dim) {
     return (unsigned)g;
 }
 
+// out[j] = sc_j * sum_b partials[j*nb + b], j < nout.
+struct ScaleVec {
+    double v[kMaxCols + 2];
+};
+
+__global__ __launch_bounds__(kThreads) void finalize_scaled_kernel(const double *__restrict__ partials, int nb,
+                                                                   ScaleVec sc, double *__restrict__ out) {
+    __shared__ double sh[kWaves];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) s += partials[(size_t)j * nb + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += sh[w];
+        out[j] = sc.v[j] * t;
+    }
+}
+
 hipError_t finalize(const double *partials, unsigned nb, int ncols, double scale, double *out, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(ncols), dim3(kThreads), 0, s, partials, (int)nb, scale, out);
     return hipGetLastError();
@@ -248,44 +329,89 @@ hipError_t finalize(const double *partials, unsigned nb, int ncols, double scale
     do {                                                                                         \
         if ((ncols) <= 4) hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__);                            \
         else if ((ncols) <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                       \
+        else if ((ncols) <= 12) hipLaunchKernelGGL(KERNEL<12>, __VA_ARGS__);                     \
         else if ((ncols) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                     \
+        else if ((ncols) <= 24) hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__);                     \
         else if ((ncols) <= 32) hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                     \
+        else if ((ncols) <= 48) hipLaunchKernelGGL(KERNEL<48>, __VA_ARGS__);                     \
         else hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__);                                        \
     } while (0)
+// Same, for kernels templated on the column bound and the input type.
+#define PD_DISPATCH_COLS_T(ncols, T, KERNEL, ...)                                                 \
+    do {                                                                                         \
+        if ((ncols) <= 4) hipLaunchKernelGGL((KERNEL<4, T>), __VA_ARGS__);                       \
+        else if ((ncols) <= 8) hipLaunchKernelGGL((KERNEL<8, T>), __VA_ARGS__);                  \
+        else if ((ncols) <= 12) hipLaunchKernelGGL((KERNEL<12, T>), __VA_ARGS__);                \
+        else if ((ncols) <= 16) hipLaunchKernelGGL((KERNEL<16, T>), __VA_ARGS__);                \
+        else if ((ncols) <= 24) hipLaunchKernelGGL((KERNEL<24, T>), __VA_ARGS__);                \
+        else if ((ncols) <= 32) hipLaunchKernelGGL((KERNEL<32, T>), __VA_ARGS__);                \
+        else if ((ncols) <= 48) hipLaunchKernelGGL((KERNEL<48, T>), __VA_ARGS__);                \
+        else hipLaunchKernelGGL((KERNEL<64, T>), __VA_ARGS__);                                   \
+    } while (0)
+
+hipError_t finalize_scaled(const double *partials, unsigned nb, int nout, const ScaleVec &sc, double *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(finalize_scaled_kernel, dim3(nout), dim3(kThreads), 0, s, partials, (int)nb, sc, out);
+    return hipGetLastError();
+}
 
 }  // namespace
 
 int vec_grid() { return kGrid; }
-size_t partial_doubles() { return (size_t)kGrid * kMaxCols; }
+size_t partial_doubles() { return (size_t)kGrid * (kMaxCols + 2); }
 
-hipError_t launch_gemvt(const double *Q, int64_t ld, int ncols, int64_t dim, const double *p, double *partials,
-                        double *c_dev, hipStream_t s) {
+hipError_t launch_project(const double *Q, int64_t ld, int ncols, int64_t dim, const void *p, bool p_f32, double sp,
+                          const double *sc_host, const double *d_host, double *partials, double *out_dev,
+                          hipStream_t s) {
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     unsigned nb = grid_for(dim);
-    PD_DISPATCH_COLS(ncols, gemvt_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, p, partials);
+    SmallVec d;
+    for (int j = 0; j < 64; ++j) d.v[j] = j < ncols ? d_host[j] : 0.0;
+    if (p_f32)
+        PD_DISPATCH_COLS_T(ncols, float, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
+                           static_cast<const float *>(p), sp, d, partials);
+    else
+        PD_DISPATCH_COLS_T(ncols, double, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
+                           static_cast<const double *>(p), sp, d, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return finalize(partials, nb, ncols, 1.0, c_dev, s);
+    ScaleVec f;
+    for (int j = 0; j < kMaxCols + 2; ++j) f.v[j] = j < ncols ? sc_host[j] : 1.0;
+    return finalize_scaled(partials, nb, ncols + 2, f, out_dev, s);
 }
 
-hipError_t launch_update_gemvt(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c,
-                               const double *pin, double *pout, double *partials, double *c2_dev, hipStream_t s) {
+hipError_t launch_update_project(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
+                                 const double *sc_host, const double *d_host, const void *p, bool p_f32, double sp,
+                                 double *out, float *out32, double *partials, double *out_dev, hipStream_t s) {
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     unsigned nb = grid_for(dim);
-    PD_DISPATCH_COLS(ncols, update_gemvt_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, c, pin, pout,
-                     partials);
+    SmallVec sc, d;
+    for (int j = 0; j < 64; ++j) {
+        sc.v[j] = j < ncols ? sc_host[j] : 0.0;
+        d.v[j] = j < ncols ? d_host[j] : 0.0;
+    }
+    if (p_f32)
+        PD_DISPATCH_COLS_T(ncols, float, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
+                           c_dev, sc, d, static_cast<const float *>(p), sp, out, out32, partials);
+    else
+        PD_DISPATCH_COLS_T(ncols, double, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols,
+                           dim, c_dev, sc, d, static_cast<const double *>(p), sp, out, out32, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return finalize(partials, nb, ncols, 1.0, c2_dev, s);
+    ScaleVec f;
+    for (int j = 0; j < kMaxCols + 2; ++j) f.v[j] = j < ncols ? sc_host[j] : 1.0;
+    return finalize_scaled(partials, nb, ncols + 1, f, out_dev, s);
 }
 
-hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c,
-                              const double *pin, double *pout, double *partials, double *nrm2_dev,
+hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
+                              const double *sc_host, double *v, float *out32, double *partials, double *nrm2_dev,
                               hipStream_t s) {
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     unsigned nb = grid_for(dim);
-    PD_DISPATCH_COLS(ncols, update_norm_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, c, pin, pout,
-                     partials);
+    SmallVec sc;
+    for (int j = 0; j < 64; ++j) sc.v[j] = j < ncols ? sc_host[j] : 0.0;
+    PD_DISPATCH_COLS(ncols, update_norm_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, c_dev, sc, v,
+                     out32, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize(partials, nb, 1, 1.0, nrm2_dev, s);

@@ -39,7 +39,8 @@ class LanczosInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("iterations_f32", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("converged", ctypes.c_int), ("residual", ctypes.c_double), ("monopole_min", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("sigma_seconds_f64", ctypes.c_double),
-                ("sigma_seconds_f32", ctypes.c_double), ("fallback_used", ctypes.c_int)]
+                ("sigma_seconds_f32", ctypes.c_double), ("fallback_used", ctypes.c_int),
+                ("reorth_second_passes", ctypes.c_int)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -277,6 +278,7 @@ class GroundState:
     sigma_seconds_f32: float
     fallback_used: bool
     status: int
+    reorth_second_passes: int = 0
 
 
 def make_opts(krylov=50, tol=1e-10, max_restarts=1000, mode=0, start="e1", seed=0, precision="f64",
@@ -327,7 +329,8 @@ def lanczos_ground(basis: Basis, eps, V, x0=None, want_psi=True, workspace=None,
                        iterations_f32=info.iterations_f32, restarts=info.restarts, converged=bool(info.converged),
                        residual=info.residual, monopole_min=info.monopole_min, seconds=info.seconds,
                        sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32,
-                       fallback_used=bool(info.fallback_used), status=st)
+                       fallback_used=bool(info.fallback_used), status=st,
+                       reorth_second_passes=info.reorth_second_passes)
 
 
 @dataclass
