@@ -5,7 +5,7 @@
 // longest-processing-time order) and runs the whole restarted Lanczos
 // iteration of Sec. 3.4 for it: the product (the same per-row hop code as
 // the single-instance sigma), Gram-Schmidt against all stored vectors
-// applied twice, the tridiagonal eigensolver (bisection + inverse
+// (a second pass only when needed), the tridiagonal eigensolver (bisection + inverse
 // iteration, one lane), the restart, the convergence test of Eq. convergence
 // and the occupation numbers -- all without returning to the host.  The
 // Krylov vectors of an instance live in a per-workgroup slot of the caller's
@@ -86,6 +86,8 @@ struct Shared {
     double scratch[kMaxWaves * 8];
     double alpha[kMaxKrylovB], beta[kMaxKrylovB], y[kMaxKrylovB];
     double c[kMaxKrylovB + 8], red[8];
+    double sc[kMaxKrylovB + 1];   // column scales: q_j = sc[j] * (stored column j)
+    double cs[kMaxKrylovB + 8];   // update coefficients of the stored columns
     double A[kMaxKrylovB * kMaxKrylovB], v[kMaxKrylovB];
     double theta;
     int idx, flag, abort;
@@ -189,7 +191,8 @@ __device__ void wg_sigma(const Instance &I, const Team &T, const Shared &sh, con
     }
 }
 
-// c[j] = Q[j] . p for j < nc (c in LDS).
+// c[j] = Q[j] . p for j < nc (c in LDS).  Every thread loads its 8 columns
+// together (indices clamped to the last column; c beyond nc is not used).
 __device__ bool wg_gemvt(const Args &A, Team &T, const double *Q, int64_t ld, int nc, const double *p, Shared &sh) {
     for (int j0 = 0; j0 < nc; j0 += 8) {
         double acc[8];
@@ -197,22 +200,51 @@ __device__ bool wg_gemvt(const Args &A, Team &T, const double *Q, int64_t ld, in
         for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
         for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
             const double pi = p[i];
+            double q[8];
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj)
-                if (j0 + jj < nc) acc[jj] += Q[(int64_t)(j0 + jj) * ld + i] * pi;
+            for (int jj = 0; jj < 8; ++jj) q[jj] = Q[(int64_t)(j0 + jj < nc ? j0 + jj : nc - 1) * ld + i];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) acc[jj] += q[jj] * pi;
         }
         if (!team_sum<8>(A, T, acc, sh, sh.c + j0)) return false;
     }
     return true;
 }
 
-// p -= sum_j c[j] Q[j] (j < nc); ||p||^2 to sh.red[0].
-__device__ bool wg_update(const Args &A, Team &T, const double *Q, int64_t ld, int nc, double *p, Shared &sh) {
+// p = sp * p - da * qa - db * qb in place (the recurrence terms known before
+// the projection); ||p||^2 after and ||sp * p||^2 to sh.red[0], sh.red[1].
+__device__ bool wg_shift(const Args &A, Team &T, double *p, double sp, const double *qa, double da,
+                         const double *qb, double db, Shared &sh) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
+        const double pf = sp * p[i];
+        const double ps = pf - da * qa[i] - db * qb[i];
+        p[i] = ps;
+        acc[0] += ps * ps;
+        acc[1] += pf * pf;
+    }
+    return team_sum<2>(A, T, acc, sh, sh.red);
+}
+
+// out = p - sum_{j < nc} (q_j . p) q_j with q_j = sc_j Qt_j and the raw dot
+// products Qt_j . p in sh.c; ||out||^2 to sh.red[0].  out may equal p.
+__device__ bool wg_update_to(const Args &A, Team &T, const double *Q, int64_t ld, int nc, const double *p,
+                             double *out, Shared &sh) {
+    if ((int)threadIdx.x < kMaxKrylovB + 8)
+        sh.cs[threadIdx.x] = (int)threadIdx.x < nc ? sh.sc[threadIdx.x] * sh.sc[threadIdx.x] * sh.c[threadIdx.x]
+                                                   : 0.0;
+    __syncthreads();
     double acc[1] = {0.0};
     for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
         double v = p[i];
-        for (int j = 0; j < nc; ++j) v -= Q[(int64_t)j * ld + i] * sh.c[j];
-        p[i] = v;
+        for (int j0 = 0; j0 < nc; j0 += 8) {
+            double q[8];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) q[jj] = Q[(int64_t)(j0 + jj < nc ? j0 + jj : nc - 1) * ld + i];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) v -= q[jj] * sh.cs[j0 + jj];
+        }
+        out[i] = v;
         acc[0] += v * v;
     }
     return team_sum<1>(A, T, acc, sh, sh.red);
@@ -268,6 +300,15 @@ __device__ void solve_instance(const Args &A, const Instance &I, double *slot, T
         ok = team_sum<1>(A, T, acc, sh, sh.red) && wg_scale(A, T, w, 1.0 / sqrt(sh.red[0]), Q, sh);
     }
 
+    // Gram-Schmidt as in the single-instance solver: the recurrence terms
+    // sigma q_k + beta_{k-1} q_{k-1} (sigma = alpha_{k-1}, or the previous
+    // Ritz value) are subtracted first, one classical pass follows, and a
+    // second one only when ||v|| < ||ps|| / sqrt(2) or ||v|| < ||H q_k|| / 128.
+    // Columns are stored unnormalised with their scales in sh.sc.
+    constexpr double kEta2 = 0.5, kTau2 = 1.0 / (128.0 * 128.0);
+    double theta = 0.0;
+    if (threadIdx.x == 0) sh.sc[0] = 1.0;
+    __syncthreads();
     for (cycle = 0; ok; ++cycle) {
         int m_eff = m;
         for (int k = 0; k < m; ++k) {
@@ -275,15 +316,31 @@ __device__ void solve_instance(const Args &A, const Instance &I, double *slot, T
             wg_sigma(I, T, sh, qk, p);
             __syncthreads();
             ++iterations;
+            const double sigma = k > 0 ? sh.alpha[k - 1] : theta;
+            const double da = sigma * sh.sc[k];
+            const double db = k > 0 ? sh.beta[k - 1] * sh.sc[k - 1] : 0.0;
+            if (!(ok = wg_shift(A, T, p, sh.sc[k], qk, da, k > 0 ? qk - ld : qk, db, sh))) break;
+            const double nrm_ps = sh.red[0], nrm_hq = sh.red[1];
             if (!(ok = wg_gemvt(A, T, Q, ld, k + 1, p, sh))) break;
-            const double alpha = sh.c[k];
-            if (!(ok = wg_update(A, T, Q, ld, k + 1, p, sh))) break;
-            if (!(ok = wg_gemvt(A, T, Q, ld, k + 1, p, sh))) break;
-            if (!(ok = wg_update(A, T, Q, ld, k + 1, p, sh))) break;
-            const double beta = sqrt(fmax(sh.red[0], 0.0));
+            const double alpha = sigma + sh.sc[k] * sh.c[k];
+            const bool store = k + 1 < m;
+            double nrm_v = 0.0;
+            if (store || k == 0) {
+                double *out = store ? Q + (int64_t)(k + 1) * ld : w;
+                if (!(ok = wg_update_to(A, T, Q, ld, k + 1, p, out, sh))) break;
+                nrm_v = sh.red[0];
+                if (!(nrm_v >= kEta2 * nrm_ps && nrm_v >= kTau2 * nrm_hq)) {
+                    if (!(ok = wg_gemvt(A, T, Q, ld, k + 1, out, sh))) break;
+                    if (!(ok = wg_update_to(A, T, Q, ld, k + 1, out, out, sh))) break;
+                    nrm_v = sh.red[0];
+                }
+            }
+            const double beta = sqrt(fmax(nrm_v, 0.0));
+            __syncthreads();
             if (threadIdx.x == 0) {
                 sh.alpha[k] = alpha;
                 sh.beta[k] = beta;
+                if (store && beta > 0.0) sh.sc[k + 1] = 1.0 / beta;
             }
             if (k == 0) {
                 e0 = alpha + I.eshift;
@@ -291,6 +348,7 @@ __device__ void solve_instance(const Args &A, const Instance &I, double *slot, T
                 if (residual <= A.tol) converged = true;
                 if (converged || final_check) break;
             }
+            if (!store) break;
             double tnorm = 0.0;
             __syncthreads();
             for (int i = 0; i <= k; ++i) tnorm = fmax(tnorm, fabs(sh.alpha[i]) + sh.beta[i]);
@@ -298,7 +356,6 @@ __device__ void solve_instance(const Args &A, const Instance &I, double *slot, T
                 m_eff = k + 1;
                 break;
             }
-            if (k + 1 < m && !(ok = wg_scale(A, T, p, 1.0 / beta, Q + (int64_t)(k + 1) * ld, sh))) break;
         }
         if (!ok || converged || final_check) break;
         __syncthreads();
@@ -306,17 +363,20 @@ __device__ void solve_instance(const Args &A, const Instance &I, double *slot, T
             sh.flag = tridiag_lowest_work(m_eff, sh.alpha, sh.beta, &sh.theta, sh.y, sh.A, sh.v);
         __syncthreads();
         if (sh.flag != 0) break;
+        theta = sh.theta;
         // psi = Q y, normalised, becomes q_1
         {
             double acc[1] = {0.0};
             for (int64_t i = T.r0 + threadIdx.x; i < T.r1; i += blockDim.x) {
                 double v = 0.0;
-                for (int j = 0; j < m_eff; ++j) v += Q[(int64_t)j * ld + i] * sh.y[j];
+                for (int j = 0; j < m_eff; ++j) v += Q[(int64_t)j * ld + i] * (sh.y[j] * sh.sc[j]);
                 w[i] = v;
                 acc[0] += v * v;
             }
             ok = team_sum<1>(A, T, acc, sh, sh.red) && wg_scale(A, T, w, 1.0 / sqrt(sh.red[0]), Q, sh);
         }
+        if (threadIdx.x == 0) sh.sc[0] = 1.0;
+        __syncthreads();
         if (cycle >= A.max_restarts) final_check = true;
     }
 
