@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size in rows (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=5)
+    ap.add_argument("--verbose", action="store_true", help="per-cycle progress of the solves on stderr")
     ap.add_argument("--kernel-only", action="store_true",
                     help="for counter runs: one 1 GiB device copy (the known-size reference), then "
                          "--sigma-reps FP32 and FP64 products of the workload, and exit")
@@ -121,6 +122,32 @@ def cpu_baseline(om, n, eps, V, rows_req):
                        f"({rows * K:.3e} non-zeros, {dt:.1f} s)")
 
 
+def stream_probe(torch, gib=8, reps=5):
+    """Achievable HBM bandwidth on this machine, event-timed over `gib` GiB buffers:
+    a read-only stream (a sum), a device-to-device copy (read + write bytes)
+    and a fill (write only).  Returns (best, {probe: GB/s})."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    probes = {"read (sum)": (lambda: a.sum(), n * 4),
+              "copy": (lambda: b.copy_(a), 2 * n * 4),
+              "write (fill)": (lambda: b.fill_(2.0), n * 4)}
+    out = {}
+    for name, (fn, nbytes) in probes.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return max(out.values()), out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -176,7 +203,7 @@ def main():
         del x, y
     torch.cuda.empty_cache()
 
-    common = dict(krylov=args.krylov, tol=args.tol, start="random", seed=1, want_psi=False)
+    common = dict(krylov=args.krylov, tol=args.tol, start="random", seed=1, want_psi=False, verbose=args.verbose)
     nb_mixed = pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f32")
     ws = pairdiag.device_buffer(nb_mixed)
 
@@ -221,20 +248,21 @@ def main():
         lo = net.logits(om, eps, V)
         x0 = basis.warm_start(torch.tensor(lo, dtype=torch.float32))
         warm_r = pairdiag.lanczos_ground(basis, eps, V, x0=x0, fallback=True, precision="f32", workspace=ws,
-                                         krylov=args.krylov, tol=args.tol, want_psi=False)
+                                         krylov=args.krylov, tol=args.tol, want_psi=False, verbose=args.verbose)
         torch.cuda.synchronize()
         warm_total = time.perf_counter() - t
         warm_info = dict(weights=os.path.relpath(wpath, ROOT), seconds_including_network=warm_total,
                          fallback_used=warm_r.fallback_used)
         log(f"warm (mixed): E0={warm_r.E0:.12f} products={warm_r.iterations} {warm_total:.2f} s incl. network")
 
+    del ws
+    torch.cuda.empty_cache()
+
     batched = None
     if not args.no_batched:
         insts = [inputs.family3_instance(s) for s in range(args.batched_count)]
         dims = np.array([math.comb(i[0], i[1]) for i in insts])
         Ks = np.array([i[1] * (i[0] - i[1]) for i in insts])
-        del ws
-        torch.cuda.empty_cache()
         rb = pairdiag.lanczos_ground_batched(insts, krylov=20, tol=args.tol)   # includes the autotuner
         rb = pairdiag.lanczos_ground_batched(insts, krylov=20, tol=args.tol)   # tuned
         bnnz = float((rb.iterations * dims * Ks).sum())
@@ -256,6 +284,8 @@ def main():
         log(f"cpu baseline: {cpu['value']:.3e} nnz/s on {cpu['cores']} threads")
 
     traffic = traffic_from_profiles(f"sigma_f32_omega{om}_n{n}_counters")
+    achievable, probes = stream_probe(torch)
+    log("stream probes (8 GiB): " + ", ".join(f"{k} {v:.0f} GB/s" for k, v in probes.items()))
     out = {
         "metric": "sigma nonzeros/s + HBM GB/s; time-to-E0 at Omega=32,n=16, plain vs mixed vs warm",
         "value": value,
@@ -283,6 +313,10 @@ def main():
                              "gather_model_GBps": balg32 / avg32 / 1e9 if n32 else None,
                              "measured_GBps": traffic / avg32 / 1e9 if (traffic and n32) else None,
                              "measured_frac_of_peak": traffic / avg32 / 1e9 / PEAK_HBM_GBS
+                             if (traffic and n32) else None,
+                             "achievable_GBps": achievable,
+                             "achievable_probes_GBps": probes,
+                             "measured_frac_of_achievable": traffic / avg32 / 1e9 / achievable
                              if (traffic and n32) else None,
                              "peak_GBps": PEAK_HBM_GBS}},
         "cpu_baseline": cpu,

@@ -4,7 +4,7 @@
 // atomic counter over instances sorted largest-first by the host, i.e. the
 // longest-processing-time order) and runs the whole restarted Lanczos
 // iteration of Sec. 3.4 for it: the product (the same per-row hop code as
-// the single-instance sigma), Gram-Schmidt against all stored vectors
+// the single-instance sigma, with its per-lane slots in dynamic LDS), Gram-Schmidt against all stored vectors
 // (a second pass only when needed), the tridiagonal eigensolver (bisection + inverse
 // iteration, one lane), the restart, the convergence test of Eq. convergence
 // and the occupation numbers -- all without returning to the host.  The
@@ -99,6 +99,7 @@ struct Team {
     int64_t r0, r1;       // rows owned by this member
     int *ctl;             // barrier count at ctl[0], generation at ctl[32], mailbox at ctl[64]
     double *part;         // 2 x 8 x G partial sums
+    uint32_t *pre;        // the workgroup's per-lane LDS slots of the sigma
     int parity;
 };
 
@@ -174,8 +175,8 @@ template <int NN, bool COMP>
 __device__ void wg_sigma_nn(const Instance &I, const Team &T, const Shared &sh, const double *x, double *y) {
     const int ks = I.nn + 2;
     for (int64_t row = T.r0 + threadIdx.x; row < T.r1; row += blockDim.x)
-        y[row] = sigma_detail::sigma_row_walk<uint32_t, double, NN, COMP>(row, I.dim, I.omega, ks, sh.Ct, sh.Vs, sh.ds,
-                                                                     I.dsum, x);
+        y[row] = sigma_detail::sigma_row<uint32_t, double, NN, COMP>(row, I.dim, I.omega, ks, sh.Ct, sh.Vs, sh.ds,
+                                                                I.dsum, x, T.pre, (int)blockDim.x);
 }
 
 // Instances arrive with n <= omega - n (the host maps the others to their
@@ -419,13 +420,19 @@ __device__ void solve_instance(const Args &A, const Instance &I, double *slot, T
     __syncthreads();
 }
 
+// Dynamic LDS of the solver: the sigma's per-lane slots, 2 (kMaxPairs + 1)
+// words per thread.
+inline size_t batched_dyn_lds(int block) { return (size_t)2 * (kMaxPairs + 1) * block * sizeof(uint32_t); }
+
 __global__ __launch_bounds__(512) void batched_kernel(Args A) {
     __shared__ Shared sh;
+    extern __shared__ __align__(16) unsigned char bdyn[];
     // Phase 1 (teams > 0): large instances, one team of workgroups each
     // (team = workgroup id mod teams, member = id / teams, all members work in
     // the slot of member 0).  Phase 2: the rest, one workgroup each.  A single
     // call site of solve_instance keeps one copy of the solver in the kernel.
     Team T;
+    T.pre = reinterpret_cast<uint32_t *>(bdyn);
     int phase = A.teams > 0 ? 1 : 2;
     const int t = A.teams > 0 ? (int)(blockIdx.x % A.teams) : 0;
     for (;;) {
@@ -626,6 +633,17 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
                       double *occ_out, pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream) {
     using namespace batched;
     auto t0 = std::chrono::steady_clock::now();
+    {
+        // static Shared plus the sigma's dynamic slots exceed the default 64 KB
+        static bool raised = false;
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batched_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)batched_dyn_lds(512));
+            if (e != hipSuccess) return fail(PD_EDEVICE, "batched kernel LDS: %s", hipGetErrorString(e));
+            raised = true;
+        }
+    }
     Layout L = layout_for(count, omega, n, o->krylov);
     if (work_bytes < L.total) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
     unsigned char *base = static_cast<unsigned char *>(work);
@@ -748,7 +766,7 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
                 hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, stream, d_counter, As.n_large, d_large,
                                    d_team_ctl, kCtlInts * 8, d_error);
                 PD_HIP(hipEventRecord(e0, stream));
-                hipLaunchKernelGGL(batched_kernel, dim3(trial_grid), dim3(c), 0, stream, As);
+                hipLaunchKernelGGL(batched_kernel, dim3(trial_grid), dim3(c), batched_dyn_lds(c), stream, As);
                 PD_HIP(hipGetLastError());
                 PD_HIP(hipEventRecord(e1, stream));
                 PD_HIP(hipEventSynchronize(e1));
@@ -777,7 +795,7 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
     if (e == hipSuccess) {
         hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, cap, d_counter, n_large, d_large, d_team_ctl,
                            kCtlInts * 8, d_error);
-        hipLaunchKernelGGL(batched_kernel, dim3(L.grid), dim3(block), 0, cap, A);
+        hipLaunchKernelGGL(batched_kernel, dim3(L.grid), dim3(block), batched_dyn_lds(block), cap, A);
         e = hipStreamEndCapture(cap, &graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

@@ -169,11 +169,12 @@ __host__ __device__ inline size_t prefix_bytes(int nn) {
 }
 
 // (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
-// pre: this workgroup's prefix area (prefix_bytes); the lane uses entries
-// [i * kThreads + threadIdx.x] only.
+// pre: this workgroup's prefix area of 2 (NN + 1) * pstride words (pstride >=
+// blockDim.x); the lane uses entries [i * pstride + threadIdx.x] only.
 template <typename R, typename T, int NN, bool COMP>
 __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
-                                       const T *ds, T dsum, const T *__restrict__ x, R *pre) {
+                                       const T *ds, T dsum, const T *__restrict__ x, R *pre,
+                                       int pstride = kThreads) {
     const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
 
     // state of rank rk: greedy, orbits from the top
@@ -209,8 +210,8 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
             occ &= ~(1ull << a);
             const int j = NN - r;
             const R c0 = Ct[a * ks + j], cm = Ct[a * ks + j - 1], cp = Ct[a * ks + j + 1];
-            pre[r * kThreads + lane] = s0 - sm;
-            pre[(NN + 1 + r) * kThreads + lane] = sp - s0;
+            pre[r * pstride + lane] = s0 - sm;
+            pre[(NN + 1 + r) * pstride + lane] = sp - s0;
             rup[r] = rk + (sm - s0 - c0);
             rdn[r] = rk + (s0 - sp - cp);
             apos[r] = a;
@@ -219,8 +220,8 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
             sp += cp;
             dacc += ds[a];
         }
-        pre[NN * kThreads + lane] = s0 - sm;
-        pre[(2 * NN + 1) * kThreads + lane] = sp - s0;
+        pre[NN * pstride + lane] = s0 - sm;
+        pre[(2 * NN + 1) * pstride + lane] = sp - s0;
     }
     // Mirrored space: element dim - 1 - rank; fold the mirror into rup/rdn.
     if (COMP) {
@@ -245,8 +246,8 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
         E &= ~(1ull << b);
         const int A = (omega - 1 - b) - e;
         const int t = NN - A;
-        const R bup = pre[A * kThreads + lane] + Ct[b * ks + t];
-        const R bdn = pre[(NN + 1 + A) * kThreads + lane] + Ct[b * ks + t + 1];
+        const R bup = pre[A * pstride + lane] + Ct[b * ks + t];
+        const R bdn = pre[(NN + 1 + A) * pstride + lane] + Ct[b * ks + t + 1];
         const T *Vrow = Vs + b * omega;
         T xv[NN > 0 ? NN : 1];
 #pragma unroll
