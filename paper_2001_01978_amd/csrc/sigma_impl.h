@@ -42,12 +42,15 @@
 // lies in [0, dim), so wrap-around in intermediate sums cancels.
 #pragma once
 
+#include <algorithm>
+
 #include "pd_internal.h"
 
 namespace pd {
 namespace sigma_detail {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 512;           // default workgroup size (and per-lane slot stride)
+constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int64_t kMaxGrid = 256 * 16;
 
 template <typename R, typename T>
@@ -164,8 +167,8 @@ __device__ __forceinline__ T sigma_row_walk(int64_t row, int64_t dim, int omega,
 
 // Per-lane LDS scratch of sigma_row: 2 (NN + 1) rank words per thread.
 template <typename R>
-__host__ __device__ inline size_t prefix_bytes(int nn) {
-    return (size_t)(2 * nn + 2) * kThreads * sizeof(R);
+__host__ __device__ inline size_t prefix_bytes(int nn, int block) {
+    return (size_t)(2 * nn + 2) * block * sizeof(R);
 }
 
 // (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
@@ -263,8 +266,8 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     return acc;
 }
 
-template <typename R, typename T, int NN, bool COMP>
-__global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
+template <typename R, typename T, int NN, bool COMP, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int omega = P.omega, ks = P.ks;
     R *Ct;
@@ -293,8 +296,9 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
             const int64_t tile = s_tile;
             __syncthreads();
             if (tile >= hi) break;
-            const int64_t row = tile * kThreads + threadIdx.x;
-            if (row < dim) P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre);
+            const int64_t row = tile * BLOCK + threadIdx.x;
+            if (row < dim)
+                P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK);
         }
         // The last workgroup to finish clears the counters for the next launch.
         if (threadIdx.x == 0) {
@@ -307,29 +311,42 @@ __global__ __launch_bounds__(kThreads) void sigma_kernel(Params<R, T> P) {
         return;
     }
     for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
-        const int64_t row = tile * kThreads + threadIdx.x;
+        const int64_t row = tile * BLOCK + threadIdx.x;
         if (row >= dim) continue;
-        P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre);
+        P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK);
     }
 }
 
-template <typename R, typename T, int NN, bool COMP>
-hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
-    const size_t smem = ((table_bytes<R, T>(P.omega, P.ks) + 15) & ~size_t(15)) + prefix_bytes<R>(NN);
-    // Large pair counts with 64-bit ranks need more than the default 64 KB.
+template <typename R, typename T, int NN, bool COMP, int BLOCK>
+hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
+    // More than the default 64 KB of dynamic LDS needs the attribute.
     if (smem > 64 * 1024) {
         static bool raised = false;
         if (!raised) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            hipError_t e =
+                hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP, BLOCK>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
             if (e != hipSuccess) return e;
             raised = true;
         }
     }
+    P.ntiles = (P.dim + BLOCK - 1) / BLOCK;
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
     if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
-    hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP>), dim3((unsigned)grid), dim3(kThreads), smem, stream, P);
+    hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP, BLOCK>), dim3((unsigned)grid), dim3(BLOCK), smem, stream, P);
     return hipGetLastError();
+}
+
+// Workgroups of 512 threads unless 256 keeps more waves resident: the LDS of
+// a workgroup is the tables plus 2 (NN + 1) rank words per thread, and 160 KB
+// per CU must hold whole workgroups.
+template <typename R, typename T, int NN, bool COMP>
+hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
+    const size_t tables = (table_bytes<R, T>(P.omega, P.ks) + 15) & ~size_t(15);
+    const size_t s512 = tables + prefix_bytes<R>(NN, 512), s256 = tables + prefix_bytes<R>(NN, 256);
+    const size_t waves512 = (kLdsPerCU / s512) * 8, waves256 = std::min<size_t>((kLdsPerCU / s256) * 4, 16);
+    if (waves256 > waves512) return launch_block<R, T, NN, COMP, 256>(P, s256, stream);
+    return launch_block<R, T, NN, COMP, 512>(P, s512, stream);
 }
 
 template <typename R, typename T, bool COMP>

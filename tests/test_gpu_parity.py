@@ -190,10 +190,11 @@ def test_sigma_full_size_omega28_sampled_f64(torch_cuda, pdg, oracle_mod):
     assert np.all(np.abs(got - want) <= 2 * K * 2.0 ** -53 * bound)
 
 
-@pytest.mark.parametrize("om,n", [(28, 14), (32, 16)])
+@pytest.mark.parametrize("om,n", [(28, 14), (32, 16), (34, 17)])
 def test_sigma_full_size_dyadic_exact_sampled(torch_cuda, pdg, oracle_mod, om, n):
-    """FP64 and FP32 at Omega=28 (4.0e7 states) and Omega=32 (6.0e8 states, the
-    benchmark's space and launch): exact."""
+    """FP64 and FP32 at Omega=28 (4.0e7 states), Omega=32 (6.0e8 states, the
+    benchmark's space and launch) and Omega=34 (2.3e9 states; FP64 there runs
+    256-thread workgroups): exact."""
     torch = torch_cuda
     _, _, eps, V = inputs.dyadic_instance(om, n, 5)
     d = math.comb(om, n)
