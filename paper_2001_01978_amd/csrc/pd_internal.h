@@ -132,7 +132,6 @@ hipError_t launch_scale(const double *x, int64_t dim, double scale, double *out,
 // nrm2/sum of a vector.
 hipError_t launch_norm_sum(const double *x, int64_t dim, double *partials, double *nrm2_dev,
                            double *sum_dev, hipStream_t s);
-hipError_t launch_f32_to_f64(const float *x, int64_t dim, double *out, hipStream_t s);
 hipError_t launch_fill_random(uint64_t seed, int64_t dim, double *out, hipStream_t s);
 hipError_t launch_fill_unit(int64_t dim, int64_t index, double *out, hipStream_t s);
 hipError_t launch_copy(const double *x, int64_t dim, double *out, hipStream_t s);

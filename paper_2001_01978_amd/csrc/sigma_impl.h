@@ -90,81 +90,6 @@ __host__ __device__ inline size_t table_bytes(int omega, int ks) {
     return (((size_t)omega * ks * sizeof(R) + 15) & ~size_t(15)) + ((size_t)omega * omega + omega) * sizeof(T);
 }
 
-// (H x)[row] for one row, walking all orbits from the top and updating the
-// suffix sums in registers (no LDS scratch; lanes diverge on the occupation
-// pattern).  Used where LDS is scarce (the batched solver's workgroups).
-template <typename R, typename T, int NN, bool COMP>
-__device__ __forceinline__ T sigma_row_walk(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
-                                       const T *ds, T dsum, const T *__restrict__ x) {
-    const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
-
-    // state of rank rk: greedy, orbits from the top
-    uint64_t s = 0;
-    {
-        R rem = rk;
-        int k = NN;
-        for (int p = omega - 1; p >= 0; --p) {
-            R c = Ct[p * ks + k];
-            if (k > 0 && c <= rem) {
-                s |= 1ull << p;
-                rem -= c;
-                --k;
-            }
-        }
-    }
-
-    // rank + removed-orbit terms, occupied orbits numbered from the top
-    R rup[NN > 0 ? NN : 1], rdn[NN > 0 ? NN : 1];
-    int apos[NN > 0 ? NN : 1];
-    T dacc = T(0);
-    {
-        uint64_t occ = s;
-        R s0 = 0, sm = 0, sp = 0;
-#pragma unroll
-        for (int r = 0; r < NN; ++r) {
-            const int a = 63 - __clzll((long long)occ);
-            occ &= ~(1ull << a);
-            const int j = NN - r;
-            const R c0 = Ct[a * ks + j], cm = Ct[a * ks + j - 1], cp = Ct[a * ks + j + 1];
-            rup[r] = rk + (sm - s0 - c0);
-            rdn[r] = rk + (s0 - sp - cp);
-            apos[r] = a;
-            s0 += c0;
-            sm += cm;
-            sp += cp;
-            dacc += ds[a];
-        }
-    }
-
-    T acc = (COMP ? (dsum - dacc) : dacc) * x[row];
-    R s0 = 0, sm = 0, sp = 0;
-    int above = 0;
-    for (int p = omega - 1; p >= 0; --p) {
-        if ((s >> p) & 1ull) {
-            const int j = NN - above;
-            s0 += Ct[p * ks + j];
-            sm += Ct[p * ks + j - 1];
-            sp += Ct[p * ks + j + 1];
-            ++above;
-        } else if (NN > 0) {
-            const int t = NN - above;
-            const R bup = s0 - sm + Ct[p * ks + t];
-            const R bdn = sp - s0 + Ct[p * ks + t + 1];
-            const T *Vrow = Vs + p * omega;
-            T xv[NN > 0 ? NN : 1];
-#pragma unroll
-            for (int r = 0; r < NN; ++r) {
-                const R jt = (p > apos[r]) ? (R)(rup[r] + bup) : (R)(rdn[r] + bdn);
-                const int64_t jx = COMP ? (dim - 1 - (int64_t)jt) : (int64_t)jt;
-                xv[r] = x[jx];
-            }
-#pragma unroll
-            for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
-        }
-    }
-    return acc;
-}
-
 // Per-lane LDS scratch of sigma_row: 2 (NN + 1) rank words per thread.
 template <typename R>
 __host__ __device__ inline size_t prefix_bytes(int nn, int block) {

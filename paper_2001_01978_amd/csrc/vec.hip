@@ -232,12 +232,6 @@ __global__ __launch_bounds__(kThreads) void scale_kernel(const double *x, int64_
     }
 }
 
-__global__ __launch_bounds__(kThreads) void f32_to_f64_kernel(const float *__restrict__ x, int64_t dim,
-                                                              double *__restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) out[i] = (double)x[i];
-}
-
 __global__ __launch_bounds__(kThreads) void copy_kernel(const double *__restrict__ x, int64_t dim,
                                                         double *__restrict__ out) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
@@ -444,11 +438,6 @@ hipError_t launch_norm_sum(const double *x, int64_t dim, double *partials, doubl
 
 hipError_t launch_scale(const double *x, int64_t dim, double scale, double *out, float *out32, hipStream_t s) {
     hipLaunchKernelGGL(scale_kernel, dim3(grid_for(dim)), dim3(kThreads), 0, s, x, dim, scale, out, out32);
-    return hipGetLastError();
-}
-
-hipError_t launch_f32_to_f64(const float *x, int64_t dim, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(f32_to_f64_kernel, dim3(grid_for(dim)), dim3(kThreads), 0, s, x, dim, out);
     return hipGetLastError();
 }
 
