@@ -68,18 +68,18 @@ struct Params {
     unsigned *sched;           // 9 tile counters, zero on entry and on exit
 };
 
-// Stages the binomial table C(p, k) (p < omega, k < ks), the couplings and the
+// Stages the binomial table C(p, k) * unit (p < omega, k < ks), the couplings and the
 // pair energies into LDS; returns the three LDS arrays through the pointers.
 template <typename R, typename T>
 __device__ __forceinline__ void stage_tables(unsigned char *smem, int omega, int ks, const T *__restrict__ V,
-                                             const T *__restrict__ d, R *&Ct, T *&Vs, T *&ds) {
+                                             const T *__restrict__ d, R *&Ct, T *&Vs, T *&ds, R unit = 1) {
     Ct = reinterpret_cast<R *>(smem);
     const int ct_elems = omega * ks;
     Vs = reinterpret_cast<T *>(smem + ((ct_elems * (int)sizeof(R) + 15) & ~15));
     ds = Vs + omega * omega;
     for (int i = threadIdx.x; i < ct_elems; i += blockDim.x) {
         int p = i / ks, k = i - p * ks;
-        Ct[i] = (R)g_binom.v[p][k];
+        Ct[i] = (R)g_binom.v[p][k] * unit;
     }
     for (int i = threadIdx.x; i < omega * omega; i += blockDim.x) Vs[i] = V[i];
     for (int i = threadIdx.x; i < omega; i += blockDim.x) ds[i] = d[i];
@@ -96,14 +96,36 @@ __host__ __device__ inline size_t prefix_bytes(int nn, int block) {
     return (size_t)(2 * nn + 2) * block * sizeof(R);
 }
 
+// Buffer resource over x for the byte-offset gathers (gfx9-family word 3).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t x_resource(const T *x, int64_t dim) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(x), (short)0, (int)(uint32_t)(dim * (int64_t)sizeof(T)),
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buffer_gather(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)byte_off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)byte_off, 0, 0));
+}
+
 // (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
 // pre: this workgroup's prefix area of 2 (NN + 1) * pstride words (pstride >=
-// blockDim.x); the lane uses entries [i * pstride + threadIdx.x] only.
-template <typename R, typename T, int NN, bool COMP>
+// blockDim.x); the lane uses entries [i * pstride + threadIdx.x] only.  xr: x_resource of x.
+// BUF (32-bit ranks, FP32, dim * sizeof(T) < 2^32 only): every rank quantity is in
+// units of sizeof(T) bytes -- Ct holds C(p, k) * sizeof(T) (stage_tables) and
+// the lane's rank is scaled once -- so a target rank is directly the byte
+// offset of a 32-bit-offset buffer load through xr (no 64-bit address
+// arithmetic).  The greedy unranking stays exact: every compared entry is at
+// most dim * sizeof(T) < 2^32.
+template <typename R, typename T, int NN, bool COMP, bool BUF = false>
 __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
-                                       const T *ds, T dsum, const T *__restrict__ x, R *pre,
-                                       int pstride = kThreads) {
-    const R rk = COMP ? (R)(dim - 1 - row) : (R)row;
+                                       const T *ds, T dsum, const T *__restrict__ x, R *pre, int pstride,
+                                       __amdgpu_buffer_rsrc_t xr) {
+    constexpr R U = BUF ? (R)sizeof(T) : (R)1;   // rank unit
+    const R rk = (COMP ? (R)(dim - 1 - row) : (R)row) * U;
 
     // state of rank rk: greedy, orbits from the top
     uint64_t s = 0;
@@ -155,8 +177,8 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     if (COMP) {
 #pragma unroll
         for (int r = 0; r < NN; ++r) {
-            rup[r] = (R)(dim - 1) - rup[r];
-            rdn[r] = (R)(dim - 1) - rdn[r];
+            rup[r] = (R)(dim - 1) * U - rup[r];
+            rdn[r] = (R)(dim - 1) * U - rdn[r];
         }
     }
 
@@ -183,7 +205,10 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
             // r < A: a_r above b (down hop); otherwise below (up hop)
             const R jt = COMP ? ((r < A) ? (R)(rdn[r] - bdn) : (R)(rup[r] - bup))
                               : ((r < A) ? (R)(rdn[r] + bdn) : (R)(rup[r] + bup));
-            xv[r] = x[(int64_t)jt];
+            if constexpr (BUF)
+                xv[r] = buffer_gather<T>(xr, (uint32_t)jt);
+            else
+                xv[r] = x[(int64_t)jt];
         }
 #pragma unroll
         for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
@@ -191,15 +216,16 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     return acc;
 }
 
-template <typename R, typename T, int NN, bool COMP, int BLOCK>
+template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
 __global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int omega = P.omega, ks = P.ks;
     R *Ct;
     T *Vs, *ds;
-    stage_tables<R, T>(smem, omega, ks, P.V, P.d, Ct, Vs, ds);
+    stage_tables<R, T>(smem, omega, ks, P.V, P.d, Ct, Vs, ds, BUF ? (R)sizeof(T) : (R)1);
     R *pre = reinterpret_cast<R *>(smem + ((table_bytes<R, T>(omega, ks) + 15) & ~size_t(15)));
     __syncthreads();
+    const __amdgpu_buffer_rsrc_t xr = x_resource<T>(P.x, P.dim);   // used by the BUF gathers only
 
     const int64_t dim = P.dim;
     if ((gridDim.x & 7) == 0 && P.ntiles >= (int64_t)gridDim.x) {
@@ -223,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
             if (tile >= hi) break;
             const int64_t row = tile * BLOCK + threadIdx.x;
             if (row < dim)
-                P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK);
+                P.y[row] = sigma_row<R, T, NN, COMP, BUF>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK, xr);
         }
         // The last workgroup to finish clears the counters for the next launch.
         if (threadIdx.x == 0) {
@@ -238,18 +264,18 @@ __global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
     for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
         const int64_t row = tile * BLOCK + threadIdx.x;
         if (row >= dim) continue;
-        P.y[row] = sigma_row<R, T, NN, COMP>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK);
+        P.y[row] = sigma_row<R, T, NN, COMP, BUF>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK, xr);
     }
 }
 
-template <typename R, typename T, int NN, bool COMP, int BLOCK>
+template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
 hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
     // More than the default 64 KB of dynamic LDS needs the attribute.
     if (smem > 64 * 1024) {
         static bool raised = false;
         if (!raised) {
             hipError_t e =
-                hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP, BLOCK>),
+                hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP, BLOCK, BUF>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
             if (e != hipSuccess) return e;
             raised = true;
@@ -258,7 +284,8 @@ hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
     P.ntiles = (P.dim + BLOCK - 1) / BLOCK;
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
     if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
-    hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP, BLOCK>), dim3((unsigned)grid), dim3(BLOCK), smem, stream, P);
+    hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP, BLOCK, BUF>), dim3((unsigned)grid), dim3(BLOCK), smem, stream,
+                       P);
     return hipGetLastError();
 }
 
@@ -270,8 +297,15 @@ hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
     const size_t tables = (table_bytes<R, T>(P.omega, P.ks) + 15) & ~size_t(15);
     const size_t s512 = tables + prefix_bytes<R>(NN, 512), s256 = tables + prefix_bytes<R>(NN, 256);
     const size_t waves512 = (kLdsPerCU / s512) * 8, waves256 = std::min<size_t>((kLdsPerCU / s256) * 4, 16);
-    if (waves256 > waves512) return launch_block<R, T, NN, COMP, 256>(P, s256, stream);
-    return launch_block<R, T, NN, COMP, 512>(P, s512, stream);
+    // Byte-offset buffer gathers (FP32, every byte offset of x within 32 bits;
+    // measured slower than 64-bit global loads for FP64 gathers).
+    constexpr bool kCanBuf = sizeof(R) == 4 && sizeof(T) == 4;
+    const bool buf = kCanBuf && (uint64_t)P.dim * sizeof(T) < (uint64_t(1) << 32);
+    if (waves256 > waves512)
+        return buf ? launch_block<R, T, NN, COMP, 256, kCanBuf>(P, s256, stream)
+                   : launch_block<R, T, NN, COMP, 256, false>(P, s256, stream);
+    return buf ? launch_block<R, T, NN, COMP, 512, kCanBuf>(P, s512, stream)
+               : launch_block<R, T, NN, COMP, 512, false>(P, s512, stream);
 }
 
 template <typename R, typename T, bool COMP>
