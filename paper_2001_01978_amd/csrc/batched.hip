@@ -65,8 +65,10 @@ struct Args {
     int *error;           // set when a team barrier times out
     long long spin_limit;
     const double *coef;
-    double *slots;
+    double *slots;          // team slots (instances [0, n_large))
     int64_t slot_doubles;
+    double *slots2;         // one slot per workgroup for the rest
+    int64_t slot2_doubles;
     double tol;
     int max_restarts;
     Result *res;
@@ -469,7 +471,7 @@ __global__ __launch_bounds__(512) void batched_kernel(Args A) {
             idx = __builtin_amdgcn_readfirstlane(sh.idx);
             __syncthreads();
             if (idx >= A.count) break;
-            slot = A.slots + (int64_t)blockIdx.x * A.slot_doubles;
+            slot = A.slots2 + (int64_t)blockIdx.x * A.slot2_doubles;
         }
         solve_instance(A, A.inst[idx], slot, T, sh);
         if (phase == 1) {
@@ -507,8 +509,9 @@ int device_cus() {
 struct Layout {
     size_t inst = 0, sample = 0, coef = 0, counter = 0, team_ctl = 0, team_part = 0, res = 0, occ = 0, slots = 0,
            total = 0;
-    int64_t slot_doubles = 0, coef_doubles = 0, occ_doubles = 0;
+    int64_t slot_doubles = 0, slot2_doubles = 0, coef_doubles = 0, occ_doubles = 0;
     int grid = 0, m_max = 0, nslots = 0;
+    size_t slots2 = 0;
     int teams = 0, n_large = 0;
 };
 
@@ -524,37 +527,45 @@ double instance_cost(int omega, int n, int krylov) {
 
 // Schedule: with a full grid (a multiple of 8 workgroups), 8 teams of grid/8
 // workgroups first solve the costliest instances (sorted order), then every
-// workgroup drains the rest alone.  The split s comes from the cost model:
-// phase 1 takes (cost of the first s) / (grid * team efficiency), phase 2 the
-// larger of (cost of the rest) / grid and one remaining instance times 3
-// (iteration counts of equal-size instances differ by that much); the largest
-// s within 10% of the best predicted time is taken.
+// workgroup drains the rest alone.  Cost units are those of instance_cost
+// (work of one product).  A team runs an instance at 93% of its workgroups'
+// combined rate plus a fixed overhead per product (its cross-workgroup
+// barriers): kTeamOverhead, about 57 us against the ~4e9 units/s of one
+// workgroup, both measured on 4096 instances of the batched family.  Phase 1
+// takes sum (cost/(G * 0.93) + overhead) / teams, phase 2 the larger of
+// (cost of the rest) / grid and one remaining instance times 3 (iteration
+// counts of equal-size instances differ by that much).  The split with the
+// lowest predicted time is taken: small instances stay on single workgroups,
+// where the barriers would cost more than the work.
+constexpr double kTeamEff = 0.93;
+constexpr double kTeamOverhead = 2.3e5;
 void plan_schedule(int count, const int *omega, const int *n, int krylov, int grid, const std::vector<int> &order,
                    int *teams, int *n_large) {
     *teams = 0;
     *n_large = 0;
     if (grid < 64 || grid % 8 != 0) return;
+    const int nteams = 8, G = grid / nteams;
     std::vector<double> cost(count);
     double total = 0.0;
     for (int i = 0; i < count; ++i) total += (cost[i] = instance_cost(omega[i], n[i], krylov));
-    const double team_eff = 0.95;  // barriers and shorter rows per workgroup
     std::vector<double> t(count + 1);
-    double best = 1e300, done = 0.0;
+    double best = 1e300, done = 0.0, phase1 = 0.0;
     for (int split = 0; split <= count; ++split) {
         const double rest = total - done;
         const double largest_rest = split < count ? cost[order[split]] : 0.0;
-        t[split] = done / (grid * team_eff) + std::max(rest / grid, 3.0 * largest_rest);
+        t[split] = phase1 / nteams + std::max(rest / grid, 3.0 * largest_rest);
         best = std::min(best, t[split]);
-        if (split < count) done += cost[order[split]];
+        if (split < count) {
+            done += cost[order[split]];
+            phase1 += cost[order[split]] / (G * kTeamEff) + kTeamOverhead;
+        }
     }
-    // the most team work within 10% of the best: teams keep a single slow
-    // instance off the critical path and need one Krylov slot per team only
-    for (int split = count; split >= 0; --split)
-        if (t[split] <= 1.1 * best) {
+    for (int split = 0; split <= count; ++split)
+        if (t[split] == best) {
             *n_large = split;
             break;
         }
-    if (*n_large > 0) *teams = 8;
+    if (*n_large > 0) *teams = nteams;
 }
 
 std::vector<int> cost_order(int count, const int *omega, const int *n, int krylov) {
@@ -575,12 +586,21 @@ Layout layout_for(int count, const int *omega, const int *n, int krylov) {
         L.occ_doubles += omega[i];
     }
     L.m_max = (int)std::min<int64_t>(krylov, dmax);
-    const int64_t ld = (dmax + 63) & ~int64_t(63);
-    L.slot_doubles = ((int64_t)(L.m_max + 2) * ld + 31) & ~int64_t(31);
+    auto slot_for = [krylov](int64_t d) {
+        const int64_t m = std::min<int64_t>(krylov, d), ld = (d + 63) & ~int64_t(63);
+        return ((m + 2) * ld + 31) & ~int64_t(31);
+    };
     L.grid = std::min(count, device_cus());
-    plan_schedule(count, omega, n, krylov, L.grid, cost_order(count, omega, n, krylov), &L.teams, &L.n_large);
-    // every instance on teams: one Krylov slot per team; otherwise one per workgroup
-    L.nslots = (L.teams > 0 && L.n_large == count) ? L.teams : L.grid;
+    const std::vector<int> order = cost_order(count, omega, n, krylov);
+    plan_schedule(count, omega, n, krylov, L.grid, order, &L.teams, &L.n_large);
+    // Team slots fit the largest instance; the single-workgroup slots fit the
+    // largest instance left after the team phase (sorted costliest first).
+    int64_t d2 = 0;
+    for (int q = L.n_large; q < count; ++q)
+        d2 = std::max<int64_t>(d2, (int64_t)binom_host(omega[order[q]], n[order[q]]));
+    L.slot_doubles = L.teams > 0 ? slot_for(dmax) : 0;
+    L.slot2_doubles = d2 > 0 ? slot_for(d2) : 0;
+    L.nslots = L.teams;
     size_t off = 0;
     L.inst = off;
     off += align256(sizeof(Instance) * (size_t)count);
@@ -599,7 +619,9 @@ Layout layout_for(int count, const int *omega, const int *n, int krylov) {
     L.occ = off;
     off += align256(sizeof(double) * (size_t)L.occ_doubles);
     L.slots = off;
-    off += sizeof(double) * (size_t)L.slot_doubles * (size_t)L.nslots;
+    off += align256(sizeof(double) * (size_t)L.slot_doubles * (size_t)L.nslots);
+    L.slots2 = off;
+    off += sizeof(double) * (size_t)L.slot2_doubles * (size_t)L.grid;
     L.total = off;
     return L;
 }
@@ -723,6 +745,8 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
     A.coef = d_coef;
     A.slots = d_slots;
     A.slot_doubles = L.slot_doubles;
+    A.slots2 = reinterpret_cast<double *>(base + L.slots2);
+    A.slot2_doubles = L.slot2_doubles;
     A.tol = o->tol;
     A.max_restarts = o->max_restarts;
     A.res = d_res;

@@ -71,6 +71,31 @@ def test_batched_family_with_large_instances(pdg):
         assert math.isclose(r.occ[q].sum(), 2 * n, abs_tol=1e-8)
 
 
+def test_batched_team_and_single_workgroup_phases(pdg, oracle_mod):
+    """260 instances fill a 256-workgroup grid: the costliest run on teams of
+    workgroups (bounded barriers, shared partial sums), the rest on single
+    workgroups.  Team-solved instances agree with the single-instance path,
+    small ones with dense diagonalisation."""
+    insts = [inputs.family3_instance(s) for s in range(256)]
+    insts += [inputs.family3_instance(9000 + s, omega=22, n=11) for s in range(4)]
+    r = pdg.lanczos_ground_batched(insts, krylov=20, tol=1e-10, seed=5)
+    assert r.status == pdg.PD_OK and r.converged.all()
+    if r.info["grid"] < 256:
+        pytest.skip("fewer than 256 compute units: no team phase")
+    assert r.info["teams"] == 8 and 0 < r.info["large"] < len(insts), r.info
+    dims = np.array([math.comb(i[0], i[1]) for i in insts])
+    for q in np.argsort(-dims)[:4]:
+        om, n, eps, V = insts[q]
+        b = pdg.Basis(om, n, store_states=False)
+        s = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=2, want_psi=False)
+        assert abs(r.E0[q] - s.E0) <= 1e-10 * abs(s.E0), (q, om, n)
+        assert np.allclose(r.occ[q], s.occ, atol=1e-8)
+    for q in np.argsort(dims)[:4]:
+        om, n, eps, V = insts[q]
+        e0 = oracle_mod.dense_ground(om, n, eps, V)[0]
+        assert abs(r.E0[q] - e0) <= 1e-10 * abs(e0), (q, om, n)
+
+
 def test_batched_edge_instances(pdg, oracle_mod):
     rng = np.random.default_rng(4)
     insts = []
