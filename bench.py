@@ -124,12 +124,17 @@ def cpu_baseline(om, n, eps, V, rows_req):
 
 def stream_probe(torch, gib=8, reps=5):
     """Achievable HBM bandwidth on this machine, event-timed over `gib` GiB buffers:
-    a read-only stream (a sum), a device-to-device copy (read + write bytes)
-    and a fill (write only).  Returns (best, {probe: GB/s})."""
+    a read-only stream (a sum), 16 columns read together (a matrix-vector
+    product, the access pattern of a Gram-Schmidt pass), a device-to-device
+    copy (read + write bytes) and a fill (write only).  Returns (best,
+    {probe: GB/s})."""
     n = gib * (1 << 30) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    cols = a.view(16, n // 16)          # 16 columns streamed together, as in a Gram-Schmidt pass
+    v = torch.ones(n // 16, dtype=torch.float32, device="cuda")
     probes = {"read (sum)": (lambda: a.sum(), n * 4),
+              "read 16 columns (gemv)": (lambda: torch.mv(cols, v), n * 4 + (n // 16) * 4),
               "copy": (lambda: b.copy_(a), 2 * n * 4),
               "write (fill)": (lambda: b.fill_(2.0), n * 4)}
     out = {}
@@ -143,7 +148,7 @@ def stream_probe(torch, gib=8, reps=5):
         e1.record()
         torch.cuda.synchronize()
         out[name] = nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
-    del a, b
+    del a, b, cols, v
     torch.cuda.empty_cache()
     return max(out.values()), out
 
@@ -318,6 +323,8 @@ def main():
                              "achievable_probes_GBps": probes,
                              "measured_frac_of_achievable": traffic / avg32 / 1e9 / achievable
                              if (traffic and n32) else None,
+                             "measured_frac_of_16_column_stream": traffic / avg32 / 1e9
+                             / probes["read 16 columns (gemv)"] if (traffic and n32) else None,
                              "peak_GBps": PEAK_HBM_GBS}},
         "cpu_baseline": cpu,
         "time_to_E0_s": {"f64": plain.seconds if plain else None, "mixed": mixed.seconds,
