@@ -101,8 +101,12 @@ pd_status pd_basis_unrank(pd_basis b, const int64_t *ranks_dev, int64_t count,
  * The coefficients are kept in the handle's device block: when they differ
  * from the previous call on this handle they are uploaded on `stream` and
  * the stream is synchronised; otherwise the call is fully asynchronous.
- * Calls with different coefficients on one handle must be issued in order
- * (one stream, or synchronised by the caller).
+ * The same block holds the kernel's per-XCD tile counters (zero between
+ * launches), so calls on one handle must not overlap in time: issue them on
+ * one stream, or synchronise between streams.  For concurrent products,
+ * create one handle per stream (without stored states a handle takes
+ * pd_basis_bytes(omega, n, 0), about 50 KB).  pd_lanczos_ground keeps its
+ * own copy of the block in its workspace and is not restricted this way.
  */
 pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
                    const void *x_dev, void *y_dev, hipStream_t stream);
