@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 time-to-E0 solve")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned-warm-start time-to-E0 solve")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-instance batched solve")
+    ap.add_argument("--no-starts", action="store_true", help="skip the E1 and HF start solves (context)")
+    ap.add_argument("--no-prev", action="store_true",
+                    help="skip the previous-solution start (couplings x1.01 from the converged state)")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size in rows (0: auto)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -167,7 +170,10 @@ def main():
     om, n = args.omega, args.n
     _, _, eps, V = inputs.c5_instance(om, n, seed=0)
     K = n * (om - n)
+    tb = time.perf_counter()
     basis = pairdiag.Basis(om, n, store_states=False)
+    torch.cuda.synchronize()
+    basis_seconds = time.perf_counter() - tb
     D = basis.dim
     log(f"workload omega={om} n={n} dim={D} hops/row={K}")
 
@@ -212,8 +218,9 @@ def main():
     nb_mixed = pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f32")
     ws = pairdiag.device_buffer(nb_mixed)
 
-    def solve(precision):
-        return pairdiag.lanczos_ground(basis, eps, V, precision=precision, workspace=ws, **common)
+    def solve(precision, want_psi=False):
+        kw = dict(common, want_psi=want_psi)
+        return pairdiag.lanczos_ground(basis, eps, V, precision=precision, workspace=ws, **kw)
 
     for w in range(args.warmup):
         r = solve("f32")
@@ -222,7 +229,7 @@ def main():
     t0 = time.perf_counter()
     results = []
     for k in range(args.steps):
-        r = solve("f32")
+        r = solve("f32", want_psi=(k == args.steps - 1 and not args.no_prev))
         results.append(r)
         log(f"step {k}: E0={r.E0:.12f} rho={r.residual:.2e} products={r.iterations} ({r.iterations_f32} f32) "
             f"{r.seconds:.2f} s")
@@ -243,6 +250,35 @@ def main():
         r64 = solve("f64")
         plain = r64
         log(f"plain f64: E0={r64.E0:.12f} products={r64.iterations} {r64.seconds:.2f} s")
+
+    # Previous-solution start: the next problem of a self-consistent sweep,
+    # here the same instance with the couplings scaled by 1.01, started from
+    # the converged state of the timed solve, against a random start.
+    prev = None
+    if not args.no_prev and mixed.psi is not None:
+        VB = np.asarray(V) * 1.01
+        kw = dict(krylov=args.krylov, tol=args.tol, want_psi=False, precision="f32", workspace=ws,
+                  verbose=args.verbose)
+        rp = pairdiag.lanczos_ground(basis, eps, VB, x0=mixed.psi, **kw)
+        rr = pairdiag.lanczos_ground(basis, eps, VB, start="random", seed=1, **kw)
+        prev = dict(change="couplings x1.01", seconds_previous_start=rp.seconds, products_previous_start=rp.iterations,
+                    seconds_random_start=rr.seconds, products_random_start=rr.iterations,
+                    E0_rel_diff=abs(rp.E0 - rr.E0) / abs(rr.E0))
+        log(f"previous-solution start: {rp.iterations} products {rp.seconds:.2f} s vs random {rr.iterations} "
+            f"products {rr.seconds:.2f} s")
+        mixed.psi = None
+        torch.cuda.empty_cache()
+
+    # The deterministic starts of the paper (E1) and of the Hartree-Fock state, for context.
+    starts = None
+    if not args.no_starts:
+        starts = {}
+        for st in ("e1", "hf"):
+            kw = dict(common, start=st)
+            r_s = pairdiag.lanczos_ground(basis, eps, V, precision="f32", workspace=ws, **kw)
+            starts[st] = dict(seconds=r_s.seconds, products=r_s.iterations, converged=r_s.converged,
+                              E0_rel_diff_vs_random=abs(r_s.E0 - mixed.E0) / abs(mixed.E0))
+            log(f"start {st}: {r_s.iterations} products {r_s.seconds:.2f} s")
 
     warm_r, warm_info = None, None
     wpath = os.path.join(ROOT, "paper_2001_01978_amd", "weights", f"warm_o{om}_n{n}.npz")
@@ -338,6 +374,9 @@ def main():
                                  "mixed": mixed.reorth_second_passes,
                                  "warm": warm_r.reorth_second_passes if warm_r else None},
         "warm": warm_info,
+        "previous_solution_start": prev,
+        "mixed_other_starts": starts,
+        "basis_create_seconds": basis_seconds,
         "batched": batched,
         "sigma": sig,
     }
