@@ -12,6 +12,7 @@ Functions and the passages they follow:
   lanczos_ground                                          Sec. 3.4, Alg. lanczos, full reorthogonalisation,
                                                           restart with the ground Ritz vector, Eq. convergence
   occupations, monopole_min                               Sec. 4.3 outputs N_Occup and Monopole_Min
+  blocked_instance, odd_ground                            Sec. 2 Eq. hamiltonian3 (blocking), Sec. 4.2 Block, Sec. 4.3 N_Occup
   richardson_evb                                          constant-G check (Richardson equations, eigenvalue form)
   pbcs_vector                                             number-projected product start vector (warm start)
   mlp_*                                                   FP64 reference of the warm-start network
@@ -294,6 +295,42 @@ def _finish(omega, basis, psi, theta, iterations, restarts, residual):
     psi = _normalise_sign(psi)
     return dict(E0=float(theta), psi=psi, occ=occupations(omega, basis, psi),
                 iterations=iterations, restarts=restarts, residual=float(residual))
+
+
+# ---------------------------------------------------------------- odd mass (Sec. 2, Eq. hamiltonian3)
+
+def blocked_instance(omega: int, eps, V, b: int):
+    """eps and V of H_b's pair part: orbit b (0-based) removed (Eq. hamiltonian3)."""
+    eps, V = _check_h(omega, eps, V)
+    keep = [i for i in range(omega) if i != b]
+    return eps[keep].copy(), V[np.ix_(keep, keep)].copy()
+
+
+def odd_ground(omega: int, n: int, eps, V, block: int = 0, solver: str = "dense", **lanczos_kw):
+    """2n+1 particles, blocking approximation.  H_b = eps_b + the pair
+    Hamiltonian of Eq. hamiltonian2 on the omega-1 orbits other than b.
+    block (Sec. 4.2, Block): b in 1..omega solves that block; 0 solves all
+    and keeps the lowest.  N_Occup (Sec. 4.3): 1 on the blocked orbit.
+    solver: 'dense' (explicit matrix) or 'lanczos' (the oracle's Lanczos).
+    Returns dict(E, block, E_blocks, occ) with E_blocks NaN where not solved."""
+    eps, V = _check_h(omega, eps, V)
+    if not (omega >= 2 and 0 <= n <= omega - 1 and 0 <= block <= omega):
+        raise ValueError("odd system needs omega >= 2, 0 <= n <= omega-1, 0 <= block <= omega")
+    blocks = range(omega) if block == 0 else [block - 1]
+    E_blocks = np.full(omega, np.nan)
+    occ_blocks = {}
+    for b in blocks:
+        eps_b, V_b = blocked_instance(omega, eps, V, b)
+        if solver == "dense":
+            e0, _, occ_b, _ = dense_ground(omega - 1, n, eps_b, V_b)
+        else:
+            r = lanczos_ground(omega - 1, n, eps_b, V_b, **lanczos_kw)
+            e0, occ_b = r["E0"], r["occ"]
+        E_blocks[b] = eps[b] + e0
+        occ_blocks[b] = occ_b
+    best = min(blocks, key=lambda b: (E_blocks[b], b))
+    occ = np.insert(occ_blocks[best], best, 1.0)
+    return dict(E=float(E_blocks[best]), block=best + 1, E_blocks=E_blocks, occ=occ)
 
 
 # ---------------------------------------------------------------- Richardson (constant G)
