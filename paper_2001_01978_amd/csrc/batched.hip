@@ -532,7 +532,8 @@ double instance_cost(int omega, int n, int krylov) {
 // combined rate plus a fixed overhead per product (its cross-workgroup
 // barriers): kTeamOverhead, about 57 us against the ~4e9 units/s of one
 // workgroup, both measured on 4096 instances of the batched family.  Phase 1
-// takes sum (cost/(G * 0.93) + overhead) / teams, phase 2 the larger of
+// takes sum (cost/(G * 0.93) + overhead) / teams, but no less than its
+// costliest instance on one team; phase 2 the larger of
 // (cost of the rest) / grid and one remaining instance times 3 (iteration
 // counts of equal-size instances differ by that much).  The split with the
 // lowest predicted time is taken: small instances stay on single workgroups,
@@ -553,7 +554,11 @@ void plan_schedule(int count, const int *omega, const int *n, int krylov, int gr
     for (int split = 0; split <= count; ++split) {
         const double rest = total - done;
         const double largest_rest = split < count ? cost[order[split]] : 0.0;
-        t[split] = phase1 / nteams + std::max(rest / grid, 3.0 * largest_rest);
+        // Phase 1 cannot end before its costliest instance (order[0]) does on
+        // one team, however few instances share the teams.
+        const double p1 = split > 0 ? std::max(phase1 / nteams, cost[order[0]] / (G * kTeamEff) + kTeamOverhead)
+                                    : 0.0;
+        t[split] = p1 + std::max(rest / grid, 3.0 * largest_rest);
         best = std::min(best, t[split]);
         if (split < count) {
             done += cost[order[split]];
@@ -590,9 +595,12 @@ Layout layout_for(int count, const int *omega, const int *n, int krylov) {
         const int64_t m = std::min<int64_t>(krylov, d), ld = (d + 63) & ~int64_t(63);
         return ((m + 2) * ld + 31) & ~int64_t(31);
     };
-    L.grid = std::min(count, device_cus());
+    // The whole device when teams are planned (a few large instances still
+    // fill every compute unit); one workgroup per instance otherwise.
+    L.grid = device_cus();
     const std::vector<int> order = cost_order(count, omega, n, krylov);
     plan_schedule(count, omega, n, krylov, L.grid, order, &L.teams, &L.n_large);
+    if (L.teams == 0) L.grid = std::min(count, L.grid);
     // Team slots fit the largest instance; the single-workgroup slots fit the
     // largest instance left after the team phase (sorted costliest first).
     int64_t d2 = 0;
@@ -755,7 +763,11 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
     // ---- autotune the workgroup size on a sample spread over the cost range
     double tune_seconds = 0.0;
     int tuned = 0;
-    if (block == 0) {
+    if (block == 0 && count <= kSample) {
+        // The tuning sample would be the whole batch, solved once per
+        // candidate: take the size the tuner picks on large batches.
+        block = 512;
+    } else if (block == 0) {
         std::vector<int64_t> key = {count, L.grid, o->krylov};
         for (int i = 0; i < count; ++i) key.push_back(sorted[i].dim);
         std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -96,6 +96,24 @@ def test_batched_team_and_single_workgroup_phases(pdg, oracle_mod):
         assert abs(r.E0[q] - e0) <= 1e-10 * abs(e0), (q, om, n)
 
 
+def test_batched_few_large_instances_use_the_whole_device(pdg):
+    """Fewer instances than compute units, all large: teams spread them over
+    every workgroup slot of the device instead of one workgroup each; three
+    teams find no instance and go straight to the (empty) single phase."""
+    insts = [inputs.family3_instance(9100 + s, omega=21, n=10) for s in range(5)]
+    r = pdg.lanczos_ground_batched(insts, krylov=20, tol=1e-10, seed=7)
+    assert r.status == pdg.PD_OK and r.converged.all()
+    if r.info["grid"] < 64:
+        pytest.skip("fewer than 64 compute units: no team phase")
+    assert r.info["teams"] == 8 and r.info["large"] == len(insts), r.info
+    assert r.info["grid"] > len(insts) and r.info["tuned"] == 0 and r.info["block"] == 512
+    for q, (om, n, eps, V) in enumerate(insts):
+        b = pdg.Basis(om, n, store_states=False)
+        s = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=2, want_psi=False)
+        assert abs(r.E0[q] - s.E0) <= 1e-10 * abs(s.E0), (q, om, n)
+        assert np.allclose(r.occ[q], s.occ, atol=1e-8)
+
+
 def test_batched_edge_instances(pdg, oracle_mod):
     rng = np.random.default_rng(4)
     insts = []
