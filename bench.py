@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 time-to-E0 solve")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned-warm-start time-to-E0 solve")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-instance batched solve")
+    ap.add_argument("--no-odd", action="store_true", help="skip the odd-system (all blocks) solve")
     ap.add_argument("--no-starts", action="store_true", help="skip the E1 and HF start solves (context)")
     ap.add_argument("--no-prev", action="store_true",
                     help="skip the previous-solution start (couplings x1.01 from the converged state)")
@@ -318,6 +319,23 @@ def main():
         log(f"batched: {batched['converged']}/{args.batched_count} converged in {batched['seconds']:.2f} s, "
             f"{batched['nnz_per_s']:.3e} nnz/s")
 
+    # Odd particle number (blocking): every block of an omega = 25, 12-pair
+    # instance (2n + 1 = 25 particles), each block 12 pairs on 24 orbits.
+    odd = None
+    if not args.no_odd:
+        oo, on = 25, 12
+        _, _, oeps, oV = inputs.c5_instance(oo, on, seed=0)
+        okw = dict(krylov=20, tol=args.tol, start="random", seed=1)
+        pairdiag.lanczos_ground_odd(oo, on, oeps, oV, **okw)
+        ro = pairdiag.lanczos_ground_odd(oo, on, oeps, oV, **okw)
+        odim = math.comb(oo - 1, on)
+        odd = dict(workload=f"odd system omega={oo}, {2 * on + 1} particles, all {oo} blocks of {on} pairs on "
+                            f"{oo - 1} orbits (dim {odim} each), FP64, krylov 20",
+                   seconds=ro.seconds, products=ro.iterations, converged=ro.converged, E=ro.E, block=ro.block,
+                   nnz_per_s=ro.iterations * odim * on * (oo - 1 - on) / ro.seconds,
+                   status=pairdiag._STATUS.get(ro.status))
+        log(f"odd: E={ro.E:.12f} block {ro.block}, {ro.iterations} products in {ro.seconds:.2f} s")
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -378,6 +396,7 @@ def main():
         "mixed_other_starts": starts,
         "basis_create_seconds": basis_seconds,
         "batched": batched,
+        "odd": odd,
         "sigma": sig,
     }
     print(json.dumps(out), flush=True)

@@ -114,8 +114,9 @@ pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
 /* ------------------------------------------------------------------ Lanczos
  * Restarted, fully reorthogonalised Lanczos (Sec. 3.4, Alg. lanczos): Krylov
  * vectors are orthogonalised against all stored vectors (classical
- * Gram-Schmidt, applied a second time when the first pass cancels more than
- * 127/128 of the norm), the lowest Ritz pair of the krylov x krylov
+ * Gram-Schmidt after the three-term recurrence, applied a second time when the
+ * first pass leaves less than 1/sqrt(2) of the norm it started from, or less
+ * than 1/128 of ||H q||), the lowest Ritz pair of the krylov x krylov
  * tridiagonal matrix comes from Sturm bisection and inverse iteration, and
  * the iteration restarts from the
  * ground-state Ritz vector.  Convergence (Eq. convergence): the restarted
@@ -183,23 +184,28 @@ pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size
  * from o; krylov <= 32).  Limits per instance: omega <= 32, min(n, omega-n) <= 12
  * (instances with n > omega - n are solved as their particle-hole complement,
  * an exact identity: E0 = E0' + sum_i (2 eps_i + V_ii), <N_i> = 2 - <N_i>').
- * Inputs (host): omega[count], n[count]; eps_packed: the omega_i pair energies
- * of each instance back to back; V_packed: the omega_i x omega_i row-major
+ * Inputs (host): omega[count], n[count]; eps_packed: the omega_i single-particle
+ * energies of each instance back to back; V_packed: the omega_i x omega_i row-major
  * couplings back to back.  Outputs (host): E0_out[count]; occ_out (optional):
  * sum(omega_i) doubles, packed like eps; info_out (optional, per instance:
  * iterations, restarts, converged, residual); binfo (optional).
  * block: workgroup size 128, 256 or 512, or 0 to autotune it on a sample of the
- * batch (the choice is cached per batch shape for the life of the process).
- * Instances whose cost exceeds half the mean load of one workgroup are first
- * solved by teams of workgroups (8 teams of grid/8) that split the rows and
- * meet at a bounded-wait barrier; if a wait times out (another kernel holding
- * compute units) the call returns PD_EDEVICE.  The workspace holds one Krylov
- * slot per workgroup sized for the largest instance.  Returns PD_ENOCONV if any instance missed the tolerance (all
- * outputs filled).  info_out[i].seconds is the device time the instance took.
+ * batch (the choice is cached per batch shape for the life of the process;
+ * batches of at most 32 instances, where the sample would be the whole batch,
+ * take 512 untuned).  A cost model (work per product, team barrier overhead)
+ * picks how many of the costliest instances are first solved by teams of
+ * workgroups (8 teams of grid/8, grid = all compute units) that split the
+ * rows and meet at a bounded-wait barrier; if a wait times out (another
+ * kernel holding compute units) the call returns PD_EDEVICE.  Without teams
+ * the grid is min(count, compute units).  The workspace holds one Krylov slot
+ * per team sized for the largest instance and one per workgroup sized for the
+ * largest instance left to single workgroups.  Returns PD_ENOCONV if any
+ * instance missed the tolerance (all outputs filled).  info_out[i].seconds is
+ * the device time the instance took.
  * Synchronises `stream`. */
 typedef struct {
     int block;             /* workgroup size used */
-    int grid;              /* persistent workgroups (one per compute unit, at most count) */
+    int grid;              /* persistent workgroups (one per compute unit; at most count without teams) */
     int tuned;             /* 1 if this call ran the autotuner */
     int teams;             /* workgroup teams for the large instances (0: none) */
     int team_size;         /* workgroups per team */
@@ -216,6 +222,44 @@ pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, c
                                     const double *V_packed, const pd_lanczos_opts *o, int block,
                                     void *work_dev, size_t work_bytes, double *E0_out, double *occ_out,
                                     pd_lanczos_info *info_out, pd_batch_info *binfo, hipStream_t stream);
+
+/* ------------------------------------------------------------------ odd mass
+ * 2n + 1 particles in the blocking approximation (Sec. 2, Eq. hamiltonian3):
+ * the unpaired particle on orbit b keeps pairs out of b, so the seniority-one
+ * space is a direct sum of blocks b = 1..omega with
+ *     H_b = eps_b + H(n pairs on the omega - 1 orbits other than b),
+ * H being Eq. hamiltonian2 with eps and V restricted to those orbits.
+ * block (the Block argument of Sec. 4.2): b in [1, omega] solves H_b only;
+ * 0 solves every H_b and returns the lowest (ties: the smallest b).
+ * route (block = 0 only; 0 for block != 0): PD_ODD_AUTO picks PD_ODD_BATCHED
+ * when a block fits pd_lanczos_ground_batched (omega - 1 <= 32,
+ * min(n, omega-1-n) <= 12, krylov <= 32) and has at most 2^22 states, else
+ * PD_ODD_SEQUENTIAL.  BATCHED solves the omega blocks in one batched launch
+ * (FP64, RANDOM starts with seed o->seed + b - 1, workgroup size 512);
+ * SEQUENTIAL builds one basis of the reduced space in the workspace and runs
+ * pd_lanczos_ground once per block with o as given.
+ * Inputs (host): eps[omega] (single-particle energies), V[omega*omega]
+ * (symmetric, finite), as for pd_lanczos_ground; omega in [2, 62];
+ * n in [0, omega - 1] is the number of pairs (N_Pairs = n + 1/2).
+ * o->start must not be PD_START_USER.
+ * work_dev: device, 256-byte aligned, pd_odd_workspace_bytes(...) bytes.
+ * Outputs (host): *E = the lowest solved E_b, eps_b included;
+ * block_out (optional) its b (1-based); E_blocks (optional, omega doubles)
+ * E_b of each block, NaN for blocks not solved; occ (optional, omega
+ * doubles) the chosen block's <N_i>, with 1 on orbit b (Sec. 4.3, N_Occup);
+ * info (optional) sums iterations, restarts, products and device times over
+ * the blocks solved, residual = the largest, converged = all, monopole_min =
+ * the smallest diagonal element over the solved blocks, seconds = the call.
+ * Returns PD_ENOCONV (outputs filled) if a block missed the tolerance;
+ * PD_ERANGE if the reduced space exceeds what sigma (or a forced batched
+ * route) handles; PD_EINVAL / PD_ENOMEM on bad arguments or a short
+ * workspace.  Synchronises `stream`. */
+enum { PD_ODD_AUTO = 0, PD_ODD_SEQUENTIAL = 1, PD_ODD_BATCHED = 2 };
+size_t pd_odd_workspace_bytes(int omega, int n, int block, int route, const pd_lanczos_opts *o);
+pd_status pd_lanczos_ground_odd(int omega, int n, const double *eps, const double *V, int block, int route,
+                                const pd_lanczos_opts *o, void *work_dev, size_t work_bytes, double *E,
+                                int *block_out, double *E_blocks, double *occ, pd_lanczos_info *info,
+                                hipStream_t stream);
 
 /* ------------------------------------------------------------------ warm start
  * A small network maps an instance to one logit l_i per orbit; sigmoid(l_i)

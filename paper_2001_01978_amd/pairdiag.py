@@ -83,6 +83,9 @@ SIGNATURES = {
     "pd_mlp_backward": (I, [ctypes.POINTER(MlpShape), P, P, P, I, P, SZ, P, P, P]),
     "pd_mlp_adam": (I, [I64, P, P, P, P, I, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, ctypes.c_float, P]),
+    "pd_odd_workspace_bytes": (SZ, [I, I, I, I, ctypes.POINTER(LanczosOpts)]),
+    "pd_lanczos_ground_odd": (I, [I, I, P, P, I, I, ctypes.POINTER(LanczosOpts), P, SZ, ctypes.POINTER(D),
+                                  ctypes.POINTER(I), P, P, ctypes.POINTER(LanczosInfo), P]),
     "pd_batched_workspace_bytes": (SZ, [I, P, P, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_ground_batched": (I, [I, P, P, P, P, ctypes.POINTER(LanczosOpts), I, P, SZ, P, P,
                                       ctypes.POINTER(LanczosInfo), ctypes.POINTER(BatchInfo), P]),
@@ -391,3 +394,60 @@ def lanczos_ground_batched(instances, krylov=20, tol=1e-10, max_restarts=1000, s
                        residual=np.array([f.residual for f in infos]),
                        seconds=np.array([f.seconds for f in infos]),
                        info={k: getattr(bi, k) for k, _ in BatchInfo._fields_}, status=st)
+
+
+ODD_ROUTE = {"auto": 0, "sequential": 1, "batched": 2}
+
+
+@dataclass
+class OddGroundState:
+    E: float
+    block: int
+    E_blocks: np.ndarray
+    occ: np.ndarray
+    iterations: int
+    iterations_f32: int
+    restarts: int
+    converged: bool
+    residual: float
+    monopole_min: float
+    seconds: float
+    reorth_second_passes: int
+    status: int
+
+
+def odd_workspace_bytes(omega: int, n: int, block=0, route="auto", **kw) -> int:
+    o = make_opts(**kw)
+    return int(load().pd_odd_workspace_bytes(omega, n, block, ODD_ROUTE[route], ctypes.byref(o)))
+
+
+def lanczos_ground_odd(omega: int, n: int, eps, V, block=0, route="auto", workspace=None, device="cuda",
+                       stream=None, **kw) -> OddGroundState:
+    """Odd system of 2n+1 particles, blocking approximation (pd_lanczos_ground_odd).
+    block: 1..omega solves that block, 0 all of them (the lowest is returned)."""
+    L = load()
+    o = make_opts(**kw)
+    eps = _host_f64(eps, (omega,))
+    V = _host_f64(V, (omega, omega))
+    r = ODD_ROUTE[route]
+    nb = L.pd_odd_workspace_bytes(omega, n, block, r, ctypes.byref(o))
+    if nb == 0:
+        raise PairDiagError(PD_EINVAL, L.pd_last_error().decode())
+    if workspace is None:
+        buf, off = device_buffer(nb, device)
+    else:
+        buf, off = workspace
+    E = ctypes.c_double()
+    b = ctypes.c_int()
+    Eb = np.empty(omega)
+    occ = np.empty(omega)
+    info = LanczosInfo()
+    st = L.pd_lanczos_ground_odd(omega, n, _hp(eps), _hp(V), block, r, ctypes.byref(o),
+                                 ctypes.c_void_p(buf.data_ptr() + off), nb, ctypes.byref(E), ctypes.byref(b),
+                                 _hp(Eb), _hp(occ), ctypes.byref(info), _stream(stream))
+    _check(st, allow=(PD_ENOCONV,))
+    return OddGroundState(E=E.value, block=b.value, E_blocks=Eb, occ=occ, iterations=info.iterations,
+                          iterations_f32=info.iterations_f32, restarts=info.restarts,
+                          converged=bool(info.converged), residual=info.residual,
+                          monopole_min=info.monopole_min, seconds=info.seconds,
+                          reorth_second_passes=info.reorth_second_passes, status=st)

@@ -1,0 +1,123 @@
+"""GPU parity of the odd-system solver (blocking approximation, Sec. 2
+Eq. hamiltonian3; Block modes of Sec. 4.2) through pd_lanczos_ground_odd,
+against the oracle's odd_ground: every block energy within 1e-10 relative
+(FP64; 1e-9 mixed), the chosen block exactly, occupations within 1e-8
+(1e-7 mixed), with 1 on the blocked orbit."""
+import numpy as np
+import pytest
+
+from paper_2001_01978_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pdg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2001_01978_amd import pairdiag
+    pairdiag.load()
+    return pairdiag
+
+
+def _check(r, ref, rtol=1e-10, occ_tol=1e-8):
+    solved = ~np.isnan(ref["E_blocks"])
+    np.testing.assert_array_equal(np.isnan(r.E_blocks), ~solved)
+    np.testing.assert_allclose(r.E_blocks[solved], ref["E_blocks"][solved], rtol=rtol, atol=rtol)
+    assert r.block == ref["block"]
+    assert abs(r.E - ref["E"]) <= rtol * max(abs(ref["E"]), 1.0)
+    np.testing.assert_allclose(r.occ, ref["occ"], atol=occ_tol)
+    assert r.occ[r.block - 1] == 1.0
+
+
+@pytest.mark.parametrize("route", ["auto", "sequential", "batched"])
+@pytest.mark.parametrize("om,n", [(2, 0), (2, 1), (3, 1), (6, 0), (6, 5), (9, 4), (13, 5), (14, 7)])
+def test_odd_all_blocks_vs_oracle_dense(pdg, oracle_mod, om, n, route):
+    _, _, eps, V = inputs.c5_instance(om, n, seed=40 + om)
+    print(f"odd om={om} n={n} route={route}", flush=True)
+    r = pdg.lanczos_ground_odd(om, n, eps, V, block=0, route=route, krylov=20, tol=1e-11, start="random", seed=5)
+    assert r.status == pdg.PD_OK and r.converged
+    _check(r, oracle_mod.odd_ground(om, n, eps, V))
+
+
+def test_odd_each_block_vs_oracle(pdg, oracle_mod):
+    om, n = 11, 5
+    _, _, eps, V = inputs.c5_instance(om, n, seed=7)
+    for b in range(1, om + 1):
+        r = pdg.lanczos_ground_odd(om, n, eps, V, block=b, krylov=20, tol=1e-11)
+        assert r.status == pdg.PD_OK and r.block == b
+        _check(r, oracle_mod.odd_ground(om, n, eps, V, block=b))
+
+
+def test_odd_mixed_precision_vs_oracle(pdg, oracle_mod):
+    om, n = 15, 6
+    _, _, eps, V = inputs.c5_instance(om, n, seed=8)
+    r = pdg.lanczos_ground_odd(om, n, eps, V, route="sequential", krylov=20, tol=1e-10, precision="f32",
+                               start="random", seed=2)
+    assert r.status == pdg.PD_OK and r.converged and r.iterations_f32 > 0
+    _check(r, oracle_mod.odd_ground(om, n, eps, V), rtol=1e-9, occ_tol=1e-7)
+
+
+def test_odd_degenerate_shell_closed_form(pdg):
+    om, n, g = 12, 5, 0.3
+    r = pdg.lanczos_ground_odd(om, n, np.zeros(om), -g * np.ones((om, om)), krylov=20, tol=1e-12)
+    N = 2 * n + 1
+    exact = -g / 4 * (N - 1) * (2 * om - N - 1 + 2)
+    np.testing.assert_allclose(r.E_blocks, exact, rtol=1e-11)
+
+
+def test_odd_routes_agree_and_sampled_block_vs_oracle_lanczos(pdg, oracle_mod):
+    # 21 blocks of 10 pairs on 20 orbits (184,756 states each: many sigma tiles
+    # and a ragged last tile); batched and sequential routes, one block against
+    # the oracle's Lanczos.
+    om, n = 21, 10
+    _, _, eps, V = inputs.c5_instance(om, n, seed=9)
+    print("odd routes om=21 n=10", flush=True)
+    a = pdg.lanczos_ground_odd(om, n, eps, V, route="batched", krylov=20, tol=1e-10, start="random", seed=1)
+    s = pdg.lanczos_ground_odd(om, n, eps, V, route="sequential", krylov=20, tol=1e-10, start="random", seed=1)
+    assert a.status == pdg.PD_OK and s.status == pdg.PD_OK
+    np.testing.assert_allclose(a.E_blocks, s.E_blocks, rtol=2e-10)
+    assert a.block == s.block
+    np.testing.assert_allclose(a.occ, s.occ, atol=1e-7)
+    b = a.block
+    ref = oracle_mod.odd_ground(om, n, eps, V, block=b, solver="lanczos", krylov=30, tol=1e-10,
+                                index_mode="hash", start=inputs.random_vector(3, 184756))
+    assert abs(a.E - ref["E"]) <= 2e-10 * abs(ref["E"])
+    np.testing.assert_allclose(a.occ, ref["occ"], atol=1e-7)
+
+
+def test_odd_auto_route_above_batched_size_runs_blocks_in_turn(pdg, oracle_mod):
+    # Blocks of 12 pairs on 25 orbits (5.2e6 states) exceed the auto route's
+    # batched size: the blocks run one at a time with the options as given
+    # (FP32 products here, which the batched route does not use).
+    om, n = 26, 12
+    _, _, eps, V = inputs.c5_instance(om, n, seed=10)
+    print("odd auto om=26 n=12", flush=True)
+    r = pdg.lanczos_ground_odd(om, n, eps, V, krylov=20, tol=1e-9, precision="f32", start="random", seed=4)
+    assert r.status == pdg.PD_OK and r.converged and r.iterations_f32 > 0
+    assert not np.isnan(r.E_blocks).any()
+    assert r.E == pytest.approx(np.min(r.E_blocks), abs=0)
+    assert r.E <= r.monopole_min  # variational: the lowest level lies below every diagonal element
+    mm = min(eps[b] + np.sort(np.delete(2 * eps + np.diag(V), b))[:n].sum() for b in range(om))
+    assert r.monopole_min == pytest.approx(mm, rel=1e-14)
+    # the chosen block against the FP64 single-block solve
+    one = pdg.lanczos_ground_odd(om, n, eps, V, block=r.block, krylov=20, tol=1e-11)
+    assert abs(r.E - one.E) <= 1e-9 * abs(one.E)
+
+
+def test_odd_argument_errors(pdg):
+    _, _, eps, V = inputs.c5_instance(6, 2, seed=0)
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_odd(1, 0, eps[:1], V[:1, :1])
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_odd(6, 6, eps, V)
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_odd(6, 2, eps, V, block=7)
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_odd(6, 2, eps, V, block=2, route="batched")
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_odd(6, 2, eps, V, route="batched", krylov=40)
+    Vb = V.copy()
+    Vb[0, 1] += 1.0
+    with pytest.raises(pdg.PairDiagError):
+        pdg.lanczos_ground_odd(6, 2, eps, Vb)
