@@ -13,6 +13,8 @@ Functions and the passages they follow:
                                                           restart with the ground Ritz vector, Eq. convergence
   occupations, monopole_min                               Sec. 4.3 outputs N_Occup and Monopole_Min
   blocked_instance, odd_ground                            Sec. 2 Eq. hamiltonian3 (blocking), Sec. 4.2 Block, Sec. 4.3 N_Occup
+  diagonals, trunc_select, sigma(index_mode=              Sec. 3.5 truncation (diagonal histogram, cut, binary
+    'bsearch_truncated')                                  search in the truncated basis)
   richardson_evb                                          constant-G check (Richardson equations, eigenvalue form)
   pbcs_vector                                             number-projected product start vector (warm start)
   mlp_*                                                   FP64 reference of the warm-start network
@@ -133,13 +135,15 @@ def _check_h(omega, eps, V):
 def sigma(omega: int, n: int, eps, V, basis: np.ndarray, x, index_mode: str = "bsearch",
           rows: tuple[int, int] | None = None) -> np.ndarray:
     """y = H x over rows [r0, r1) (all rows by default).  index_mode 'bsearch'
-    (independent path) or 'hash' (the paper's fast path, used for timing)."""
+    (independent path), 'hash' (the paper's fast path, used for timing) or
+    'bsearch_truncated' (basis is a truncated space, Sec. 3.5: hops to states
+    outside it are dropped)."""
     eps, V = _check_h(omega, eps, V)
     x = _f64(x)
     r0, r1 = rows if rows is not None else (0, basis.size)
     y = np.empty(r1 - r0)
-    rc = lib().or_sigma_rows(omega, n, _p(eps), _p(V), _p(basis), basis.size,
-                             1 if index_mode == "hash" else 0, _p(x), _p(y), r0, r1)
+    mode = {"bsearch": 0, "hash": 1, "bsearch_truncated": 2}[index_mode]
+    rc = lib().or_sigma_rows(omega, n, _p(eps), _p(V), _p(basis), basis.size, mode, _p(x), _p(y), r0, r1)
     if rc != 0:
         raise RuntimeError("hop target missing from the basis")
     return y
@@ -295,6 +299,54 @@ def _finish(omega, basis, psi, theta, iterations, restarts, residual):
     psi = _normalise_sign(psi)
     return dict(E0=float(theta), psi=psi, occ=occupations(omega, basis, psi),
                 iterations=iterations, restarts=restarts, residual=float(residual))
+
+
+# ---------------------------------------------------------------- truncation (Sec. 3.5)
+
+def diagonals(omega: int, eps, V, basis: np.ndarray) -> np.ndarray:
+    """Diagonal element of every state (Eq. diagonal), summed over the occupied
+    orbits in ascending order."""
+    eps, V = _check_h(omega, eps, V)
+    d = 2.0 * eps + np.diag(V)
+    acc = np.zeros(basis.size)
+    for q in range(omega):
+        occ = ((basis >> np.uint64(q)) & np.uint64(1)).astype(bool)
+        acc[occ] += d[q]
+    return acc
+
+
+def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8):
+    """The truncation of Sec. 3.5.  If C(omega, n) exceeds `limit`, the
+    diagonal elements are counted in `bins` equal bins from the smallest to the
+    largest diagonal (Monopole_Min to Monopole_Max), the bins are accumulated
+    from the bottom, and the states in the bins up to the last one whose
+    running count is still within the limit are kept (bin 0 in any case).
+    The extreme diagonals are those of the n orbits with the smallest and the
+    largest pair energy (stable order of 2 eps_i + V_ii).
+    Returns dict(full_dim, kept, cut_bin, dmin, dmax, scale, states, ranks)."""
+    eps, V = _check_h(omega, eps, V)
+    full = binom(omega, n)
+    d = 2.0 * eps + np.diag(V)
+    order = np.argsort(d, kind="stable")
+    def extreme(orbits):
+        acc = 0.0
+        for q in sorted(int(i) for i in orbits):
+            acc += d[q]
+        return acc
+    dmin = extreme(order[:n])
+    dmax = extreme(order[omega - n:])
+    scale = bins / (dmax - dmin) if dmax > dmin else 0.0
+    basis = basis_alg1(omega, n)
+    if full <= limit:
+        return dict(full_dim=full, kept=full, cut_bin=bins - 1, dmin=dmin, dmax=dmax, scale=scale,
+                    states=basis, ranks=np.arange(full))
+    v = np.floor((diagonals(omega, eps, V, basis) - dmin) * scale)
+    b = np.where(v > 0.0, np.minimum(v, bins - 1), 0.0).astype(np.int64)
+    cum = np.cumsum(np.bincount(b, minlength=bins))
+    cut = max(int(np.searchsorted(cum, limit, side="right")) - 1, 0)
+    keep = b <= cut
+    return dict(full_dim=full, kept=int(keep.sum()), cut_bin=cut, dmin=dmin, dmax=dmax, scale=scale,
+                states=basis[keep], ranks=np.nonzero(keep)[0])
 
 
 # ---------------------------------------------------------------- odd mass (Sec. 2, Eq. hamiltonian3)

@@ -139,7 +139,9 @@ int64_t or_index_bsearch(const uint64_t *basis, int64_t dim, uint64_t t)
 }
 
 /* One row of y = H x (Sec. 3.3).  index_mode 0: binary search in basis;
- * index_mode 1: hash f.  V is omega x omega row-major. */
+ * index_mode 1: hash f; index_mode 2: binary search in a truncated basis
+ * (Sec. 3.5), where a target that is not found was truncated away and its
+ * hop is dropped.  V is omega x omega row-major. */
 static double row_value(int omega, const double *eps, const double *V, uint64_t s,
                         const uint64_t *basis, int64_t dim, int index_mode,
                         const double *x, int64_t self, int *bad)
@@ -153,7 +155,8 @@ static double row_value(int omega, const double *eps, const double *V, uint64_t 
         for (int E = 0; E < omega; ++E) {
             if ((s >> E) & 1ull) continue;
             uint64_t t = (s & ~(1ull << O)) | (1ull << E);   /* S+_E S-_O |s> */
-            int64_t j = index_mode ? or_hash(t) : or_index_bsearch(basis, dim, t);
+            int64_t j = index_mode == 1 ? or_hash(t) : or_index_bsearch(basis, dim, t);
+            if (j < 0 && index_mode == 2) continue;
             if (j < 0 || j >= dim) { *bad = 1; continue; }
             acc += V[E * omega + O] * x[j];
         }
