@@ -91,6 +91,62 @@ pd_status pd_basis_rank(pd_basis b, const uint64_t *states_dev, int64_t count,
 pd_status pd_basis_unrank(pd_basis b, const int64_t *ranks_dev, int64_t count,
                           uint64_t *states_dev, hipStream_t stream);
 
+/* ------------------------------------------------------------------ truncation
+ * Sec. 3.5: when C(omega, n) exceeds a dimension limit (Dimension_Limit), the
+ * states with the highest diagonal elements (Eq. diagonal) are left out.
+ * Every diagonal, summed over the occupied orbits in ascending order in FP64,
+ * falls in one of `bins` equal bins between dmin and dmax (the paper uses
+ * 1e8): bin = clamp(floor((diag - dmin) * scale), 0, bins - 1) with
+ * scale = bins / (dmax - dmin) (0 if dmax == dmin).  dmin and dmax are the
+ * diagonals of the n orbits with the smallest and the largest pair energy
+ * 2 eps_i + V_ii (stable order, so ties go to the lower index for dmin and to
+ * the higher index for dmax): Monopole_Min and Monopole_Max.  The bins are
+ * accumulated from the bottom; the cut bin is the last one whose running count
+ * is <= limit (bin 0 if bin 0 alone exceeds it), and a state is kept iff its
+ * bin is <= the cut bin.  Kept states keep the basis order.
+ *
+ * pd_trunc_select computes the cut (a histogram pass over the full space on
+ * the GPU; no device work if C(omega, n) <= limit).  work_dev: device, 256-byte
+ * aligned, pd_trunc_select_bytes(omega, n, bins) bytes (8 bytes per bin);
+ * bins in [1, 2^30].  Synchronises `stream`.
+ *
+ * pd_basis_create_truncated builds a basis handle over the kept states from
+ * the same eps and V (PD_EINVAL if dmin, dmax or scale come out different):
+ * its dimension is info->kept, and pd_sigma, pd_lanczos_ground and
+ * pd_occupations act on the truncated space (H restricted to it: hops to
+ * states left out are dropped).  A hop target is located by its full-space
+ * rank (Sec. 3.2) and then mapped to its row: index_mode PD_TRUNC_BITMAP uses
+ * one 16-byte word per 64 full ranks (which are kept, how many kept before);
+ * PD_TRUNC_BSEARCH binary-searches the ascending kept ranks, as the paper
+ * does for truncated spaces.  dev_buf: device, 256-byte aligned,
+ * pd_basis_truncated_bytes(omega, n, info) bytes (full dim / 4 bytes for the
+ * words, 4 or 8 bytes per kept state for its full rank: 4 when
+ * C(omega, n) < 2^32).  pd_basis_rank, pd_basis_unrank and pd_warm_start
+ * reject truncated handles.  Synchronises `stream`.
+ *
+ * pd_basis_kept_ranks: ranks_dev (device, dim int64) receives the full-space
+ * rank of every kept state, ascending.  pd_basis_truncation: whether a handle
+ * is truncated, and the full dimension. */
+enum { PD_TRUNC_BITMAP = 0, PD_TRUNC_BSEARCH = 1 };
+typedef struct {
+    int64_t full_dim;  /* C(omega, n) */
+    int64_t limit;     /* the dimension limit asked for */
+    int64_t kept;      /* states kept (= full_dim when full_dim <= limit) */
+    int64_t bins;
+    int64_t cut_bin;   /* a state is kept iff its bin <= cut_bin */
+    double dmin, dmax; /* lowest and highest diagonal element */
+    double scale;      /* bins / (dmax - dmin), 0 if dmax == dmin */
+    double cutoff;     /* upper edge of the cut bin, dmin + (cut_bin + 1) / scale (informative) */
+} pd_trunc_info;
+size_t pd_trunc_select_bytes(int omega, int n, int64_t bins);
+pd_status pd_trunc_select(int omega, int n, const double *eps, const double *V, int64_t limit, int64_t bins,
+                          void *work_dev, size_t work_bytes, pd_trunc_info *info, hipStream_t stream);
+size_t pd_basis_truncated_bytes(int omega, int n, const pd_trunc_info *info);
+pd_status pd_basis_create_truncated(int omega, int n, const double *eps, const double *V, const pd_trunc_info *info,
+                                    int index_mode, void *dev_buf, size_t bytes, hipStream_t stream, pd_basis *out);
+pd_status pd_basis_kept_ranks(pd_basis b, int64_t *ranks_dev, hipStream_t stream);
+pd_status pd_basis_truncation(pd_basis b, int *truncated, int64_t *full_dim);
+
 /* ------------------------------------------------------------------ sigma
  * y = H x, the matrix-free product of Sec. 3.3: every non-zero element is
  * generated from the pair hops |j> = S+_E S-_O |i> and located by its rank.

@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <memory>
+#include <vector>
 #include <algorithm>
 
 #include "pd_internal.h"
@@ -117,6 +119,66 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 pd_status check_basis(pd_basis b) {
     if (!b) return fail(PD_EINVAL, "basis handle is NULL");
     return PD_OK;
+}
+
+// Entry points defined on the full space only.
+pd_status check_full_basis(pd_basis b, const char *what) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (b->truncated) return fail(PD_EINVAL, "%s: not defined on a truncated basis", what);
+    return PD_OK;
+}
+
+const TruncSpace *trunc_of(pd_basis b) { return b->truncated ? &b->trunc : nullptr; }
+
+// Lowest and highest diagonal element (Monopole_Min and Monopole_Max): the
+// state of the n orbits with the smallest (largest) pair energy, ties going
+// to the lower (higher) orbit index, summed over its orbits in ascending
+// order -- the order in which the truncation kernels sum every diagonal.
+void diag_extremes(int omega, int n, const double *d, double *dmin, double *dmax) {
+    std::vector<int> idx(omega);
+    for (int i = 0; i < omega; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return d[a] < d[c]; });
+    uint64_t lo = 0, hi = 0;
+    for (int i = 0; i < n; ++i) {
+        lo |= 1ull << idx[i];
+        hi |= 1ull << idx[omega - 1 - i];
+    }
+    double a = 0.0, c = 0.0;
+    for (int q = 0; q < omega; ++q) {
+        if ((lo >> q) & 1ull) a += d[q];
+        if ((hi >> q) & 1ull) c += d[q];
+    }
+    *dmin = a;
+    *dmax = c;
+}
+
+DiagBins make_bins(int omega, const double *d, double dmin, double dmax, int64_t bins) {
+    DiagBins db;
+    std::memset(&db, 0, sizeof(db));
+    for (int i = 0; i < omega; ++i) db.d[i] = d[i];
+    db.dmin = dmin;
+    db.scale = dmax > dmin ? (double)bins / (dmax - dmin) : 0.0;
+    db.bins = bins;
+    return db;
+}
+
+struct TruncLayout {
+    size_t words, kranks, scan, total;
+    int64_t W;
+};
+TruncLayout trunc_layout(int64_t full_dim, int64_t kept) {
+    TruncLayout L;
+    L.W = (full_dim + 63) / 64;
+    size_t off = kCoefBytes;
+    L.words = off;
+    off += align256((size_t)L.W * sizeof(TruncWord));
+    L.kranks = off;
+    off += align256((size_t)kept * (trunc_ranks32(full_dim) ? 4 : 8));
+    L.scan = off;
+    off += align256(trunc_scan_words(full_dim) * sizeof(uint64_t));
+    L.total = off;
+    return L;
 }
 
 }  // namespace
@@ -236,6 +298,8 @@ pd_status pd_basis_create(int omega, int n, int store_states, void *dev_buf, siz
     b->states = store_states ? reinterpret_cast<uint64_t *>(static_cast<unsigned char *>(dev_buf) + kCoefBytes)
                              : nullptr;
     b->has_coef = 0;
+    b->truncated = 0;
+    std::memset(&b->trunc, 0, sizeof(b->trunc));
     if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
     if (b->states) {
         hipError_t e = launch_basis_build(omega, n, b->dim, b->states, stream);
@@ -263,7 +327,7 @@ const uint64_t *pd_basis_states(pd_basis b) { return b ? b->states : nullptr; }
 
 pd_status pd_basis_rank(pd_basis b, const uint64_t *states_dev, int64_t count, int64_t *ranks_dev,
                         hipStream_t stream) {
-    pd_status st = check_basis(b);
+    pd_status st = check_full_basis(b, "pd_basis_rank");
     if (st != PD_OK) return st;
     if (count < 0) return fail(PD_EINVAL, "count < 0");
     if (count == 0) return PD_OK;
@@ -276,7 +340,7 @@ pd_status pd_basis_rank(pd_basis b, const uint64_t *states_dev, int64_t count, i
 
 pd_status pd_basis_unrank(pd_basis b, const int64_t *ranks_dev, int64_t count, uint64_t *states_dev,
                           hipStream_t stream) {
-    pd_status st = check_basis(b);
+    pd_status st = check_full_basis(b, "pd_basis_unrank");
     if (st != PD_OK) return st;
     if (count < 0) return fail(PD_EINVAL, "count < 0");
     if (count == 0) return PD_OK;
@@ -307,8 +371,137 @@ pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt, 
         b->host_coef = blk;
         b->has_coef = 1;
     }
-    hipError_t e = launch_sigma(b->omega, b->n, b->dim, b->coef, dt, x_dev, y_dev, stream, blk.dsum64, blk.dsum32);
+    hipError_t e = launch_sigma(b->omega, b->n, b->dim, b->coef, dt, x_dev, y_dev, stream, blk.dsum64, blk.dsum32,
+                                trunc_of(b));
     if (e != hipSuccess) return fail(PD_EDEVICE, "sigma: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+size_t pd_trunc_select_bytes(int omega, int n, int64_t bins) {
+    if (!valid_space(omega, n) || bins < 1 || bins > kMaxTruncBins) return 0;
+    return align256(trunc_hist_doubles(bins) * sizeof(uint64_t)) + 256;
+}
+
+pd_status pd_trunc_select(int omega, int n, const double *eps, const double *V, int64_t limit, int64_t bins,
+                          void *work_dev, size_t work_bytes, pd_trunc_info *info, hipStream_t stream) {
+    if (!info) return fail(PD_EINVAL, "info is NULL");
+    if (!valid_space(omega, n)) return fail(PD_EINVAL, "invalid space omega=%d n=%d", omega, n);
+    if (limit < 1) return fail(PD_EINVAL, "limit=%lld < 1", (long long)limit);
+    if (bins < 1 || bins > kMaxTruncBins) return fail(PD_EINVAL, "bins=%lld outside [1, %lld]", (long long)bins,
+                                                      (long long)kMaxTruncBins);
+    std::unique_ptr<CoefBlock> blk(new (std::nothrow) CoefBlock);
+    if (!blk) return fail(PD_ENOMEM, "host allocation failed");
+    pd_status st = pack_coefficients(omega, n, eps, V, blk.get());
+    if (st != PD_OK) return st;
+    pd_trunc_info r;
+    std::memset(&r, 0, sizeof(r));
+    r.full_dim = (int64_t)binom_host(omega, n);
+    r.limit = limit;
+    r.bins = bins;
+    diag_extremes(omega, n, blk->d64, &r.dmin, &r.dmax);
+    const DiagBins db = make_bins(omega, blk->d64, r.dmin, r.dmax, bins);
+    r.scale = db.scale;
+    if (r.full_dim <= limit) {
+        r.kept = r.full_dim;
+        r.cut_bin = bins - 1;
+    } else {
+        const size_t need = pd_trunc_select_bytes(omega, n, bins);
+        if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+        if ((st = check_device_ptr(work_dev, "work_dev", need)) != PD_OK) return st;
+        if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
+        uint64_t *hist = static_cast<uint64_t *>(work_dev);
+        uint64_t *partial = hist + bins;
+        TruncCut *cut_dev = reinterpret_cast<TruncCut *>(static_cast<unsigned char *>(work_dev) +
+                                                         align256(trunc_hist_doubles(bins) * sizeof(uint64_t)));
+        TruncCut cut;
+        hipError_t e = launch_trunc_cut(omega, n, r.full_dim, db, limit, hist, partial, cut_dev, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&cut, cut_dev, sizeof(cut), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail(PD_EDEVICE, "truncation histogram: %s", hipGetErrorString(e));
+        r.cut_bin = cut.cut_bin;
+        r.kept = cut.kept;
+    }
+    r.cutoff = r.scale > 0.0 ? r.dmin + (double)(r.cut_bin + 1) / r.scale : r.dmin;
+    *info = r;
+    return PD_OK;
+}
+
+size_t pd_basis_truncated_bytes(int omega, int n, const pd_trunc_info *info) {
+    if (!info || !valid_space(omega, n) || info->full_dim != (int64_t)binom_host(omega, n) || info->kept < 1 ||
+        info->kept > info->full_dim)
+        return 0;
+    return trunc_layout(info->full_dim, info->kept).total;
+}
+
+pd_status pd_basis_create_truncated(int omega, int n, const double *eps, const double *V, const pd_trunc_info *info,
+                                    int index_mode, void *dev_buf, size_t bytes, hipStream_t stream, pd_basis *out) {
+    if (!out || !info) return fail(PD_EINVAL, "out and info are required");
+    if (!valid_space(omega, n)) return fail(PD_EINVAL, "invalid space omega=%d n=%d", omega, n);
+    if (index_mode != PD_TRUNC_BITMAP && index_mode != PD_TRUNC_BSEARCH)
+        return fail(PD_EINVAL, "index_mode=%d", index_mode);
+    const int64_t full_dim = (int64_t)binom_host(omega, n);
+    if (info->full_dim != full_dim || info->kept < 1 || info->kept > full_dim || info->bins < 1 ||
+        info->bins > kMaxTruncBins || info->cut_bin < 0 || info->cut_bin >= info->bins)
+        return fail(PD_EINVAL, "info does not describe a selection in this space");
+    std::unique_ptr<CoefBlock> blk(new (std::nothrow) CoefBlock);
+    if (!blk) return fail(PD_ENOMEM, "host allocation failed");
+    pd_status st = pack_coefficients(omega, n, eps, V, blk.get());
+    if (st != PD_OK) return st;
+    double dmin, dmax;
+    diag_extremes(omega, n, blk->d64, &dmin, &dmax);
+    const DiagBins db = make_bins(omega, blk->d64, dmin, dmax, info->bins);
+    if (dmin != info->dmin || dmax != info->dmax || db.scale != info->scale)
+        return fail(PD_EINVAL, "eps and V differ from the ones the selection was made with");
+    const TruncLayout L = trunc_layout(full_dim, info->kept);
+    if (bytes < L.total) return fail(PD_ENOMEM, "basis buffer %zu bytes, need %zu", bytes, L.total);
+    if ((st = check_device_ptr(dev_buf, "dev_buf", L.total)) != PD_OK) return st;
+    if (reinterpret_cast<uintptr_t>(dev_buf) & 255) return fail(PD_EINVAL, "dev_buf must be 256-byte aligned");
+    unsigned char *base = static_cast<unsigned char *>(dev_buf);
+    TruncWord *words = reinterpret_cast<TruncWord *>(base + L.words);
+    void *kranks = base + L.kranks;
+    uint64_t *scan = reinterpret_cast<uint64_t *>(base + L.scan);
+    TruncWord last;
+    hipError_t e = launch_trunc_build(omega, n, full_dim, db, info->cut_bin, words, scan, kranks, info->kept, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&last, words + (L.W - 1), sizeof(last), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "truncated basis: %s", hipGetErrorString(e));
+    const int64_t built = (int64_t)(last.base + (uint64_t)__builtin_popcountll(last.bits));
+    if (built != info->kept)
+        return fail(PD_EINVAL, "selection keeps %lld states, info says %lld", (long long)built, (long long)info->kept);
+    pd_basis b = new (std::nothrow) pd_basis_s;
+    if (!b) return fail(PD_ENOMEM, "host allocation failed");
+    b->omega = omega;
+    b->n = n;
+    b->dim = info->kept;
+    b->states = nullptr;
+    b->coef = reinterpret_cast<CoefBlock *>(dev_buf);
+    b->has_coef = 0;
+    b->truncated = 1;
+    b->trunc.full_dim = full_dim;
+    b->trunc.kept = info->kept;
+    b->trunc.kranks = kranks;
+    b->trunc.words = words;
+    b->trunc.index_mode = index_mode == PD_TRUNC_BSEARCH ? kTruncBsearch : kTruncBitmap;
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+    *out = b;
+    return PD_OK;
+}
+
+pd_status pd_basis_kept_ranks(pd_basis b, int64_t *ranks_dev, hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (!b->truncated) return fail(PD_EINVAL, "pd_basis_kept_ranks: the basis is not truncated");
+    if ((st = check_device_ptr(ranks_dev, "ranks_dev", (size_t)b->dim * 8)) != PD_OK) return st;
+    hipError_t e = launch_trunc_ranks64(b->trunc, ranks_dev, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "kept ranks: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+pd_status pd_basis_truncation(pd_basis b, int *truncated, int64_t *full_dim) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if (truncated) *truncated = b->truncated;
+    if (full_dim) *full_dim = b->truncated ? b->trunc.full_dim : b->dim;
     return PD_OK;
 }
 
@@ -383,7 +576,7 @@ pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size
     double *partials = static_cast<double *>(work_dev);
     double *occ_dev = reinterpret_cast<double *>(static_cast<unsigned char *>(work_dev) +
                                                  align256(partial_doubles() * sizeof(double)));
-    hipError_t e = launch_occupations(b->omega, b->n, b->dim, psi_dev, partials, occ_dev, stream);
+    hipError_t e = launch_occupations(b->omega, b->n, b->dim, psi_dev, partials, occ_dev, stream, trunc_of(b));
     if (e == hipSuccess) e = hipMemcpyAsync(occ_host, occ_dev, b->omega * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(PD_EDEVICE, "occupations: %s", hipGetErrorString(e));
@@ -413,7 +606,7 @@ pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, c
 }
 
 pd_status pd_warm_start(pd_basis b, const float *logits_dev, double *x0_dev, hipStream_t stream) {
-    pd_status st = check_basis(b);
+    pd_status st = check_full_basis(b, "pd_warm_start");
     if (st != PD_OK) return st;
     if ((st = check_sigma_range(b)) != PD_OK) return st;
     if ((st = check_device_ptr(logits_dev, "logits_dev", b->omega * sizeof(float))) != PD_OK) return st;

@@ -112,6 +112,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
     auto t0 = std::chrono::steady_clock::now();
     const int omega = b->omega, n = b->n;
     const int64_t dim = b->dim;
+    const TruncSpace *tr = b->truncated ? &b->trunc : nullptr;
     Layout L = layout_for(dim, o->krylov, o->precision);
     if (work_bytes < L.total)
         return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
@@ -162,6 +163,15 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             int j = 0;
             for (int q = 0; q < omega; ++q)
                 if ((st >> q) & 1ull) r += (int64_t)binom_host(q, ++j);
+            if (tr) {
+                // Its row in the truncated space (the lowest diagonal is always kept).
+                TruncWord wd;
+                PD_HIP(hipMemcpyAsync(&wd, tr->words + (r >> 6), sizeof(wd), hipMemcpyDeviceToHost, s));
+                PD_HIP(hipStreamSynchronize(s));
+                const int sh = (int)(r & 63);
+                if (!((wd.bits >> sh) & 1ull)) return fail(PD_EINVAL, "the HF state is not in the truncated space");
+                r = (int64_t)wd.base + __builtin_popcountll(wd.bits & ((1ull << sh) - 1));
+            }
             PD_HIP(launch_fill_unit(dim, r, w, s));
             break;
         }
@@ -195,7 +205,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
                 PD_HIP(dev.fetch(kOffNrm, 1));
                 PD_HIP(launch_scale(w, dim, 1.0 / std::sqrt(dev.host[kOffNrm]), q, nullptr, s));
             }
-            PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, q, p, s, dsum64, dsum32));
+            PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, q, p, s, dsum64, dsum32, tr));
             ++info.iterations;
             const double one = 1.0, zero = 0.0;
             PD_HIP(launch_project(q, ld, 1, dim, p, false, 1.0, &one, &zero, partials, scal + kOffC, s));
@@ -241,10 +251,10 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             const void *pin = f32_step ? static_cast<const void *>(y32) : static_cast<const void *>(p);
             PD_HIP(hipEventRecord(ev.a, s));
             if (f32_step) {
-                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, x32, y32, s, dsum64, dsum32));
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, x32, y32, s, dsum64, dsum32, tr));
                 ++info.iterations_f32;
             } else {
-                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32));
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32, tr));
             }
             PD_HIP(hipEventRecord(ev.b, s));
             ++info.iterations;
@@ -326,7 +336,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
     double sign = dev.host[kOffSum] < 0.0 ? -1.0 : 1.0;
     if (psi0) PD_HIP(launch_scale(Q, dim, sign, psi0, nullptr, s));
     if (occ_out) {
-        PD_HIP(launch_occupations(omega, n, dim, Q, partials, scal + kOffOcc, s));
+        PD_HIP(launch_occupations(omega, n, dim, Q, partials, scal + kOffOcc, s, tr));
         PD_HIP(dev.fetch(kOffOcc, omega));
         for (int i = 0; i < omega; ++i) occ_out[i] = dev.host[kOffOcc + i];
     }

@@ -67,6 +67,25 @@ const char *last_error();
 // Validates (omega, n, eps, V) and packs the coefficient block.
 pd_status pack_coefficients(int omega, int n, const double *eps, const double *V, CoefBlock *out);
 
+// ---------------------------------------------------------------- truncated spaces
+// Sec. 3.5: a subset of the full (omega, n) space, kept in ascending order.
+// Row i of a truncated vector is the state of full rank kranks[i].  The
+// rank -> index map is one word per 64 full ranks: which of them are kept,
+// and how many kept ranks precede the word.
+struct alignas(16) TruncWord {
+    uint64_t bits;
+    uint64_t base;
+};
+enum { kTruncBitmap = 0, kTruncBsearch = 1 };
+struct TruncSpace {
+    int64_t full_dim;
+    int64_t kept;
+    const void *kranks;       // uint32 when full_dim < 2^32, else uint64
+    const TruncWord *words;   // ceil(full_dim / 64)
+    int index_mode;           // kTruncBitmap or kTruncBsearch (target index by binary search over kranks)
+};
+inline bool trunc_ranks32(int64_t full_dim) { return full_dim < (int64_t(1) << 32); }
+
 }  // namespace pd
 
 struct pd_basis_s {
@@ -78,6 +97,8 @@ struct pd_basis_s {
     int device;
     int has_coef;            // coef holds host_coef
     pd::CoefBlock host_coef; // last block uploaded by pd_sigma
+    int truncated;           // 1: dim = trunc.kept rows of a truncated space
+    pd::TruncSpace trunc;
 };
 
 namespace pd {
@@ -94,8 +115,10 @@ hipError_t launch_basis_unrank(int omega, int n, const int64_t *ranks, int64_t c
 constexpr int kMaxSigmaPairs = 20;
 // sigma.hip: y = H x for dtype dt using coefficients at coef (device).
 // dsum64/dsum32: sum of all pair energies d_i (host copy of the block's dsum).
+// tr: nullptr for the full space, else the truncated space (dim = tr->kept).
 hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd_dtype dt,
-                        const void *x, void *y, hipStream_t s, double dsum64, float dsum32);
+                        const void *x, void *y, hipStream_t s, double dsum64, float dsum32,
+                        const TruncSpace *tr = nullptr);
 
 // vec.hip: Lanczos vector kernels.  Q holds columns of length dim with leading
 // dimension ld (elements).  `partials` is scratch of partial_doubles() doubles.
@@ -136,8 +159,31 @@ hipError_t launch_fill_random(uint64_t seed, int64_t dim, double *out, hipStream
 hipError_t launch_fill_unit(int64_t dim, int64_t index, double *out, hipStream_t s);
 hipError_t launch_copy(const double *x, int64_t dim, double *out, hipStream_t s);
 // occ[i] (device, omega doubles) = 2 sum_k psi_k^2 [bit i of state k].
+// tr: as for launch_sigma (row k is the state of full rank tr->kranks[k]).
 hipError_t launch_occupations(int omega, int n, int64_t dim, const double *psi, double *partials,
-                              double *occ_dev, hipStream_t s);
+                              double *occ_dev, hipStream_t s, const TruncSpace *tr = nullptr);
+
+// trunc.hip: selection of the kept states and construction of the map.
+struct TruncCut {
+    int64_t cut_bin;   // states whose bin <= cut_bin are kept
+    int64_t kept;
+};
+// Diagonal bins: bin(s) = clamp(floor((diag(s) - dmin) * scale), 0, bins - 1),
+// diag(s) = sum of d[q] over the occupied orbits q in ascending order (FP64).
+struct DiagBins {
+    double d[kMaxOmega];
+    double dmin, scale;
+    int64_t bins;
+};
+size_t trunc_hist_doubles(int64_t bins);
+hipError_t launch_trunc_cut(int omega, int n, int64_t full_dim, const DiagBins &db, int64_t limit, uint64_t *hist,
+                            uint64_t *partial, TruncCut *cut_dev, hipStream_t s);
+size_t trunc_scan_words(int64_t full_dim);
+constexpr int64_t kMaxTruncBins = int64_t(1) << 30;
+// out[i] = kept full rank i as int64.
+hipError_t launch_trunc_ranks64(const TruncSpace &tr, int64_t *out, hipStream_t s);
+hipError_t launch_trunc_build(int omega, int n, int64_t full_dim, const DiagBins &db, int64_t cut_bin,
+                              TruncWord *words, uint64_t *scan_tmp, void *kranks, int64_t cap, hipStream_t s);
 
 // batched.hip
 size_t batched_workspace_bytes(int count, const int *omega, const int *n, const pd_lanczos_opts *o);

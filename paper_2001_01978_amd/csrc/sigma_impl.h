@@ -111,6 +111,53 @@ __device__ __forceinline__ T buffer_gather(__amdgpu_buffer_rsrc_t rs, uint32_t b
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)byte_off, 0, 0));
 }
 
+// Truncated spaces (Sec. 3.5): x and y hold only the kept states.  A hop
+// target is still found by its full-space rank; MAP turns that rank into the
+// target's row, or drops the hop when the target was truncated away:
+//   MAP 1: one 16-byte word per 64 full ranks (kept bits, kept count before
+//          the word): row = base + popcount(bits below the rank);
+//   MAP 2: binary search over the ascending kept ranks (the paper's search
+//          for truncated spaces), all NN searches of a hop block in lockstep.
+template <typename R>
+struct TruncMap {
+    const R *kranks = nullptr;
+    const TruncWord *words = nullptr;
+    int64_t kept = 0;
+    int64_t self = 0;   // this row's index in the truncated space
+};
+
+template <typename R, typename T, int NN, int MAP>
+__device__ __forceinline__ void map_gather(const TruncMap<R> &tm, const T *__restrict__ x, const R (&jt)[NN > 0 ? NN : 1],
+                                           T (&xv)[NN > 0 ? NN : 1]) {
+    if constexpr (MAP == 1) {
+        TruncWord w[NN > 0 ? NN : 1];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) w[r] = tm.words[(int64_t)(jt[r] >> 6)];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+            const int sh = (int)(jt[r] & 63);
+            const uint64_t below = w[r].bits & ((1ull << sh) - 1);
+            const bool kept = (w[r].bits >> sh) & 1ull;
+            xv[r] = kept ? x[(int64_t)w[r].base + __popcll(below)] : T(0);
+        }
+    } else {
+        int64_t lo[NN > 0 ? NN : 1];
+#pragma unroll
+        for (int r = 0; r < NN; ++r) lo[r] = 0;
+        for (int64_t len = tm.kept; len > 1;) {
+            const int64_t half = len >> 1;
+#pragma unroll
+            for (int r = 0; r < NN; ++r) lo[r] = (tm.kranks[lo[r] + half] < jt[r]) ? lo[r] + half : lo[r];
+            len -= half;
+        }
+#pragma unroll
+        for (int r = 0; r < NN; ++r) {
+            const int64_t pos = lo[r] + (tm.kranks[lo[r]] < jt[r] ? 1 : 0);
+            xv[r] = (pos < tm.kept && tm.kranks[pos] == jt[r]) ? x[pos] : T(0);
+        }
+    }
+}
+
 // (H x)[row] for one row: NN pairs in the working space, COMP = mirrored.
 // pre: this workgroup's prefix area of 2 (NN + 1) * pstride words (pstride >=
 // blockDim.x); the lane uses entries [i * pstride + threadIdx.x] only.  xr: x_resource of x.
@@ -120,10 +167,13 @@ __device__ __forceinline__ T buffer_gather(__amdgpu_buffer_rsrc_t rs, uint32_t b
 // offset of a 32-bit-offset buffer load through xr (no 64-bit address
 // arithmetic).  The greedy unranking stays exact: every compared entry is at
 // most dim * sizeof(T) < 2^32.
-template <typename R, typename T, int NN, bool COMP, bool BUF = false>
+// MAP != 0 (truncated space): row and dim are full-space, x is indexed by
+// truncated rows (tm.self for the diagonal, map_gather for the hops).
+template <typename R, typename T, int NN, bool COMP, bool BUF = false, int MAP = 0>
 __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
                                        const T *ds, T dsum, const T *__restrict__ x, R *pre, int pstride,
-                                       __amdgpu_buffer_rsrc_t xr) {
+                                       __amdgpu_buffer_rsrc_t xr, const TruncMap<R> &tm = TruncMap<R>()) {
+    static_assert(!(BUF && MAP), "byte-offset gathers index the full space");
     constexpr R U = BUF ? (R)sizeof(T) : (R)1;   // rank unit
     const R rk = (COMP ? (R)(dim - 1 - row) : (R)row) * U;
 
@@ -182,7 +232,7 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
         }
     }
 
-    T acc = (COMP ? (dsum - dacc) : dacc) * x[row];
+    T acc = (COMP ? (dsum - dacc) : dacc) * x[MAP ? tm.self : row];
     if (NN == 0) return acc;
     // Every lane walks its own omega - NN empty orbits from the top, so all
     // lanes run the same number of hop blocks (no divergence on the
@@ -200,15 +250,24 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
         const R bdn = pre[(NN + 1 + A) * pstride + lane] + Ct[b * ks + t + 1];
         const T *Vrow = Vs + b * omega;
         T xv[NN > 0 ? NN : 1];
+        if constexpr (MAP == 0) {
 #pragma unroll
-        for (int r = 0; r < NN; ++r) {
-            // r < A: a_r above b (down hop); otherwise below (up hop)
-            const R jt = COMP ? ((r < A) ? (R)(rdn[r] - bdn) : (R)(rup[r] - bup))
-                              : ((r < A) ? (R)(rdn[r] + bdn) : (R)(rup[r] + bup));
-            if constexpr (BUF)
-                xv[r] = buffer_gather<T>(xr, (uint32_t)jt);
-            else
-                xv[r] = x[(int64_t)jt];
+            for (int r = 0; r < NN; ++r) {
+                // r < A: a_r above b (down hop); otherwise below (up hop)
+                const R jt = COMP ? ((r < A) ? (R)(rdn[r] - bdn) : (R)(rup[r] - bup))
+                                  : ((r < A) ? (R)(rdn[r] + bdn) : (R)(rup[r] + bup));
+                if constexpr (BUF)
+                    xv[r] = buffer_gather<T>(xr, (uint32_t)jt);
+                else
+                    xv[r] = x[(int64_t)jt];
+            }
+        } else {
+            R jt[NN > 0 ? NN : 1];
+#pragma unroll
+            for (int r = 0; r < NN; ++r)
+                jt[r] = COMP ? ((r < A) ? (R)(rdn[r] - bdn) : (R)(rup[r] - bup))
+                             : ((r < A) ? (R)(rdn[r] + bdn) : (R)(rup[r] + bup));
+            map_gather<R, T, NN, MAP>(tm, x, jt, xv);
         }
 #pragma unroll
         for (int r = 0; r < NN; ++r) acc += Vrow[apos[r]] * xv[r];
@@ -320,6 +379,96 @@ hipError_t dispatch_nn(const Params<R, T> &P, hipStream_t stream) {
 #undef PD_NN_CASE
         default: return hipErrorInvalidValue;
     }
+}
+
+// Truncated space: row i is the state of full rank kranks[i]; static tile
+// order (no tile counters, so calls need no stream ordering).
+template <typename R, typename T>
+struct TruncParams {
+    Params<R, T> P;       // P.dim = full dimension, P.ntiles over the kept rows
+    const R *kranks;
+    const TruncWord *words;
+    int64_t kept;
+};
+
+template <typename R, typename T, int NN, bool COMP, int BLOCK, int MAP>
+__global__ __launch_bounds__(BLOCK) void sigma_trunc_kernel(TruncParams<R, T> Q) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Params<R, T> &P = Q.P;
+    const int omega = P.omega, ks = P.ks;
+    R *Ct;
+    T *Vs, *ds;
+    stage_tables<R, T>(smem, omega, ks, P.V, P.d, Ct, Vs, ds);
+    R *pre = reinterpret_cast<R *>(smem + ((table_bytes<R, T>(omega, ks) + 15) & ~size_t(15)));
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t xr = x_resource<T>(P.x, 1);   // unused (MAP gathers)
+    TruncMap<R> tm;
+    tm.kranks = Q.kranks;
+    tm.words = Q.words;
+    tm.kept = Q.kept;
+    for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
+        const int64_t i = tile * BLOCK + threadIdx.x;
+        if (i >= Q.kept) continue;
+        tm.self = i;
+        P.y[i] = sigma_row<R, T, NN, COMP, false, MAP>((int64_t)Q.kranks[i], P.dim, omega, ks, Ct, Vs, ds, P.dsum,
+                                                        P.x, pre, BLOCK, xr, tm);
+    }
+}
+
+template <typename R, typename T, int NN, bool COMP>
+hipError_t launch_trunc_nn(TruncParams<R, T> Q, int mode, hipStream_t stream) {
+    constexpr int B = 256;
+    const size_t smem = ((table_bytes<R, T>(Q.P.omega, Q.P.ks) + 15) & ~size_t(15)) + prefix_bytes<R>(NN, B);
+    const void *fn = mode == kTruncBsearch ? reinterpret_cast<const void *>(&sigma_trunc_kernel<R, T, NN, COMP, B, 2>)
+                                           : reinterpret_cast<const void *>(&sigma_trunc_kernel<R, T, NN, COMP, B, 1>);
+    if (smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    Q.P.ntiles = (Q.kept + B - 1) / B;
+    const int64_t grid = Q.P.ntiles < kMaxGrid ? Q.P.ntiles : kMaxGrid;
+    if (mode == kTruncBsearch)
+        hipLaunchKernelGGL((sigma_trunc_kernel<R, T, NN, COMP, B, 2>), dim3((unsigned)grid), dim3(B), smem, stream, Q);
+    else
+        hipLaunchKernelGGL((sigma_trunc_kernel<R, T, NN, COMP, B, 1>), dim3((unsigned)grid), dim3(B), smem, stream, Q);
+    return hipGetLastError();
+}
+
+template <typename R, typename T, bool COMP>
+hipError_t dispatch_trunc_nn(const TruncParams<R, T> &Q, int mode, hipStream_t stream) {
+    switch (Q.P.nn) {
+#define PD_NN_CASE(K) \
+    case K: return launch_trunc_nn<R, T, K, COMP>(Q, mode, stream);
+        PD_NN_CASE(0) PD_NN_CASE(1) PD_NN_CASE(2) PD_NN_CASE(3) PD_NN_CASE(4) PD_NN_CASE(5) PD_NN_CASE(6)
+        PD_NN_CASE(7) PD_NN_CASE(8) PD_NN_CASE(9) PD_NN_CASE(10) PD_NN_CASE(11) PD_NN_CASE(12) PD_NN_CASE(13)
+        PD_NN_CASE(14) PD_NN_CASE(15) PD_NN_CASE(16) PD_NN_CASE(17) PD_NN_CASE(18) PD_NN_CASE(19)
+        PD_NN_CASE(20)
+#undef PD_NN_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, typename T>
+hipError_t launch_trunc_typed(int omega, int n, const TruncSpace &tr, const T *d, const T *V, T dsum, const T *x,
+                              T *y, hipStream_t stream) {
+    TruncParams<R, T> Q;
+    const bool comp = n > omega - n;
+    Q.P.omega = omega;
+    Q.P.nn = comp ? omega - n : n;
+    Q.P.ks = Q.P.nn + 2;
+    Q.P.dim = tr.full_dim;
+    Q.P.ntiles = 0;
+    Q.P.x = x;
+    Q.P.y = y;
+    Q.P.d = d;
+    Q.P.V = V;
+    Q.P.dsum = dsum;
+    Q.P.sched = nullptr;
+    Q.kranks = static_cast<const R *>(tr.kranks);
+    Q.words = tr.words;
+    Q.kept = tr.kept;
+    return comp ? dispatch_trunc_nn<R, T, true>(Q, tr.index_mode, stream)
+                : dispatch_trunc_nn<R, T, false>(Q, tr.index_mode, stream);
 }
 
 // y = H x with rank type R and value type T.

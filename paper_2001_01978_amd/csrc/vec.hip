@@ -260,16 +260,20 @@ __global__ __launch_bounds__(kThreads) void fill_unit_kernel(int64_t dim, int64_
 
 // Occupations: per-lane accumulators for every orbit, state from the rank.
 template <int MAXW>
+// kr32 / kr64 (at most one non-null): row k is the state of full rank kr[k]
+// (truncated space); otherwise rank k.
 __global__ __launch_bounds__(kThreads) void occupations_kernel(int omega, int n, int64_t dim,
                                                                const double *__restrict__ psi,
-                                                               double *__restrict__ partials) {
+                                                               double *__restrict__ partials,
+                                                               const uint32_t *__restrict__ kr32,
+                                                               const uint64_t *__restrict__ kr64) {
     __shared__ double sh[kWaves * MAXW];
     double acc[MAXW];
 #pragma unroll
     for (int i = 0; i < MAXW; ++i) acc[i] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < dim; k += stride) {
-        uint64_t s = 0, r = (uint64_t)k;
+        uint64_t s = 0, r = kr32 ? (uint64_t)kr32[k] : kr64 ? kr64[k] : (uint64_t)k;
         int m = n;
         for (int p = omega - 1; p >= 0; --p) {
             uint64_t c = g_binom.v[p][m];
@@ -457,12 +461,16 @@ hipError_t launch_fill_unit(int64_t dim, int64_t index, double *out, hipStream_t
 }
 
 hipError_t launch_occupations(int omega, int n, int64_t dim, const double *psi, double *partials, double *occ_dev,
-                              hipStream_t s) {
+                              hipStream_t s, const TruncSpace *tr) {
     unsigned nb = grid_for(dim);
+    const uint32_t *kr32 = tr && trunc_ranks32(tr->full_dim) ? static_cast<const uint32_t *>(tr->kranks) : nullptr;
+    const uint64_t *kr64 = tr && !trunc_ranks32(tr->full_dim) ? static_cast<const uint64_t *>(tr->kranks) : nullptr;
     if (omega <= 32)
-        hipLaunchKernelGGL(occupations_kernel<32>, dim3(nb), dim3(kThreads), 0, s, omega, n, dim, psi, partials);
+        hipLaunchKernelGGL(occupations_kernel<32>, dim3(nb), dim3(kThreads), 0, s, omega, n, dim, psi, partials, kr32,
+                           kr64);
     else
-        hipLaunchKernelGGL(occupations_kernel<64>, dim3(nb), dim3(kThreads), 0, s, omega, n, dim, psi, partials);
+        hipLaunchKernelGGL(occupations_kernel<64>, dim3(nb), dim3(kThreads), 0, s, omega, n, dim, psi, partials, kr32,
+                           kr64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize(partials, nb, omega, 2.0, occ_dev, s);

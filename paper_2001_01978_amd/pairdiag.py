@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libpairdiag.so")
 
 PD_OK, PD_EINVAL, PD_ERANGE, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV = range(6)
 PD_F64, PD_F32 = 0, 1
+PD_TRUNC_BITMAP, PD_TRUNC_BSEARCH = 0, 1
 START = {"e1": 0, "hf": 1, "random": 2, "user": 3}
 
 
@@ -50,6 +51,12 @@ class BatchInfo(ctypes.Structure):
                 ("kernel_seconds", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
+class TruncInfo(ctypes.Structure):
+    _fields_ = [("full_dim", ctypes.c_int64), ("limit", ctypes.c_int64), ("kept", ctypes.c_int64),
+                ("bins", ctypes.c_int64), ("cut_bin", ctypes.c_int64), ("dmin", ctypes.c_double),
+                ("dmax", ctypes.c_double), ("scale", ctypes.c_double), ("cutoff", ctypes.c_double)]
+
+
 class MlpShape(ctypes.Structure):
     _fields_ = [("inp", ctypes.c_int), ("h1", ctypes.c_int), ("h2", ctypes.c_int), ("out", ctypes.c_int)]
 
@@ -69,6 +76,12 @@ SIGNATURES = {
     "pd_basis_rank": (I, [P, P, I64, P, P]),
     "pd_basis_unrank": (I, [P, P, I64, P, P]),
     "pd_sigma": (I, [P, P, P, I, P, P, P]),
+    "pd_trunc_select_bytes": (SZ, [I, I, I64]),
+    "pd_trunc_select": (I, [I, I, P, P, I64, I64, P, SZ, ctypes.POINTER(TruncInfo), P]),
+    "pd_basis_truncated_bytes": (SZ, [I, I, ctypes.POINTER(TruncInfo)]),
+    "pd_basis_create_truncated": (I, [I, I, P, P, ctypes.POINTER(TruncInfo), I, P, SZ, P, ctypes.POINTER(P)]),
+    "pd_basis_kept_ranks": (I, [P, P, P]),
+    "pd_basis_truncation": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I64)]),
     "pd_lanczos_default_opts": (None, [ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_workspace_bytes": (SZ, [P, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_ground": (I, [P, P, P, ctypes.POINTER(LanczosOpts), P, SZ, P, ctypes.POINTER(D), P, P,
@@ -170,8 +183,65 @@ def tridiag_lowest(alpha, beta):
     return th.value, y
 
 
+def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8, device="cuda", stream=None) -> TruncInfo:
+    """The truncation cut of Sec. 3.5 (pd_trunc_select)."""
+    L = load()
+    eps = _host_f64(eps, (omega,))
+    V = _host_f64(V, (omega, omega))
+    nb = L.pd_trunc_select_bytes(omega, n, bins)
+    if nb == 0:
+        raise PairDiagError(PD_EINVAL, f"invalid space omega={omega} n={n} or bins={bins}")
+    buf, off = device_buffer(nb, device)
+    info = TruncInfo()
+    _check(L.pd_trunc_select(omega, n, _hp(eps), _hp(V), limit, bins, ctypes.c_void_p(buf.data_ptr() + off), nb,
+                             ctypes.byref(info), _stream(stream)))
+    del buf
+    return info
+
+
 class Basis:
-    """Handle for the space of n pairs on omega orbits (pd_basis_create)."""
+    """Handle for the space of n pairs on omega orbits (pd_basis_create), or
+    for a truncated part of it (Basis.truncated)."""
+
+    truncated_space = False
+    trunc_info = None
+
+    @classmethod
+    def truncated(cls, omega: int, n: int, eps, V, limit: int, bins: int = 10**8, index="bitmap", device="cuda",
+                  stream=None, info: TruncInfo | None = None) -> "Basis":
+        """The kept states of Sec. 3.5's truncation (pd_trunc_select +
+        pd_basis_create_truncated).  index: 'bitmap' or 'bsearch'."""
+        L = load()
+        if info is None:
+            info = trunc_select(omega, n, eps, V, limit, bins, device, stream)
+        eps = _host_f64(eps, (omega,))
+        V = _host_f64(V, (omega, omega))
+        nbytes = L.pd_basis_truncated_bytes(omega, n, ctypes.byref(info))
+        if nbytes == 0:
+            raise PairDiagError(PD_EINVAL, "bad truncation info")
+        self = cls.__new__(cls)
+        self._buf, self._off = device_buffer(nbytes, device)
+        h = ctypes.c_void_p()
+        mode = {"bitmap": PD_TRUNC_BITMAP, "bsearch": PD_TRUNC_BSEARCH}[index]
+        _check(L.pd_basis_create_truncated(omega, n, _hp(eps), _hp(V), ctypes.byref(info), mode,
+                                           ctypes.c_void_p(self._buf.data_ptr() + self._off), nbytes,
+                                           _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.omega, self.n = omega, n
+        self.dim = int(info.kept)
+        self.full_dim = int(info.full_dim)
+        self.store_states = False
+        self.device = device
+        self.truncated_space = True
+        self.trunc_info = info
+        return self
+
+    def kept_ranks(self, stream=None):
+        """Full-space ranks of the kept states (device int64, ascending)."""
+        torch = _torch()
+        out = torch.empty(self.dim, dtype=torch.int64, device=self._buf.device)
+        _check(load().pd_basis_kept_ranks(self._h, _dptr(out), _stream(stream)))
+        return out
 
     def __init__(self, omega: int, n: int, store_states: bool = True, device="cuda", stream=None):
         L = load()

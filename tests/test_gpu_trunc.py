@@ -1,0 +1,153 @@
+"""GPU parity of truncated spaces (Sec. 3.5) through the C ABI against the
+oracle: the cut (bin, kept count, extreme diagonals, scale) and the kept ranks
+bit-exact, products exact on dyadic inputs with both index modes (bitmap map
+and binary search), rounding-bounded on random inputs, ground states within
+1e-10 (FP64) / 1e-9 (mixed) of the restricted dense matrix or the oracle's
+truncated Lanczos."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2001_01978_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pdg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2001_01978_amd import pairdiag
+    pairdiag.load()
+    return pairdiag
+
+
+def _check_select(info, ref):
+    assert info.full_dim == ref["full_dim"] and info.kept == ref["kept"] and info.cut_bin == ref["cut_bin"]
+    assert info.dmin == ref["dmin"] and info.dmax == ref["dmax"] and info.scale == ref["scale"]
+
+
+@pytest.mark.parametrize("om,n,limit,bins", [(12, 6, 300, 10**8), (14, 5, 1000, 4096), (13, 9, 100, 7),
+                                             (16, 8, 5000, 10**8), (20, 6, 20000, 10**6), (18, 12, 1, 100),
+                                             (10, 4, 500, 10**8), (22, 11, 300000, 10**8)])
+def test_selection_and_kept_ranks_bit_exact(pdg, oracle_mod, om, n, limit, bins):
+    _, _, eps, V = inputs.c5_instance(om, n, seed=om + n)
+    print(f"trunc select om={om} n={n} limit={limit} bins={bins}", flush=True)
+    info = pdg.trunc_select(om, n, eps, V, limit, bins)
+    ref = oracle_mod.trunc_select(om, n, eps, V, limit, bins)
+    _check_select(info, ref)
+    b = pdg.Basis.truncated(om, n, eps, V, limit, bins, info=info)
+    assert b.dim == ref["kept"]
+    np.testing.assert_array_equal(b.kept_ranks().cpu().numpy(), ref["ranks"])
+
+
+def test_degenerate_diagonals_keep_everything(pdg, oracle_mod):
+    om, n = 12, 6
+    eps, V = np.zeros(om), -0.3 * np.ones((om, om))
+    info = pdg.trunc_select(om, n, eps, V, 10, 1000)
+    assert info.scale == 0.0 and info.cut_bin == 0 and info.kept == math.comb(om, n)
+
+
+@pytest.mark.parametrize("index", ["bitmap", "bsearch"])
+@pytest.mark.parametrize("om,n,limit", [(14, 7, 1500), (15, 4, 700), (13, 10, 150), (20, 10, 60000), (9, 0, 1),
+                                        (24, 3, 1000)])
+def test_sigma_dyadic_exact(pdg, oracle_mod, om, n, limit, index):
+    import torch
+    _, _, eps, V = inputs.dyadic_instance(om, n, seed=3)
+    ref = oracle_mod.trunc_select(om, n, eps, V, limit, 10**6)
+    b = pdg.Basis.truncated(om, n, eps, V, limit, 10**6, index=index)
+    assert b.dim == ref["kept"]
+    x = inputs.dyadic_vector(11, b.dim)
+    y_ref = oracle_mod.sigma(om, n, eps, V, ref["states"], x, index_mode="bsearch_truncated")
+    for dt in (torch.float64, torch.float32):
+        y = b.sigma(eps, V, torch.tensor(x, dtype=dt, device="cuda")).double().cpu().numpy()
+        np.testing.assert_array_equal(y, y_ref)
+
+
+def test_sigma_untruncated_handle_equals_full_space(pdg):
+    import torch
+    om, n = 18, 9
+    _, _, eps, V = inputs.c5_instance(om, n, seed=2)
+    full = pdg.Basis(om, n, store_states=False)
+    t = pdg.Basis.truncated(om, n, eps, V, full.dim, 10**8)
+    assert t.dim == full.dim
+    x = torch.tensor(inputs.random_vector(4, full.dim), device="cuda")
+    for index in ("bitmap", "bsearch"):
+        t = pdg.Basis.truncated(om, n, eps, V, full.dim, 10**8, index=index)
+        np.testing.assert_array_equal(t.sigma(eps, V, x).cpu().numpy(), full.sigma(eps, V, x).cpu().numpy())
+
+
+def test_sigma_random_rounding_bounded(pdg, oracle_mod):
+    import torch
+    om, n, limit = 22, 8, 200000
+    _, _, eps, V = inputs.c5_instance(om, n, seed=5)
+    ref = oracle_mod.trunc_select(om, n, eps, V, limit, 10**8)
+    b = pdg.Basis.truncated(om, n, eps, V, limit, 10**8)
+    x = inputs.random_vector(6, b.dim)
+    y_ref = oracle_mod.sigma(om, n, eps, V, ref["states"], x, index_mode="bsearch_truncated")
+    scale = np.abs(eps).max() * 2 + np.abs(V).sum(axis=1).max()
+    y = b.sigma(eps, V, torch.tensor(x, device="cuda")).cpu().numpy()
+    assert np.abs(y - y_ref).max() <= 1e-13 * scale * n * (om - n)
+    y32 = b.sigma(eps, V, torch.tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    assert np.abs(y32 - y_ref).max() <= 2e-6 * scale * n * (om - n)
+
+
+@pytest.mark.parametrize("index", ["bitmap", "bsearch"])
+def test_ground_state_vs_restricted_dense(pdg, oracle_mod, index):
+    om, n, limit = 14, 7, 1200
+    _, _, eps, V = inputs.c5_instance(om, n, seed=8)
+    ref = oracle_mod.trunc_select(om, n, eps, V, limit, 10**8)
+    H = oracle_mod.dense_h(om, n, eps, V)
+    k = ref["ranks"]
+    w, Z = np.linalg.eigh(H[np.ix_(k, k)])
+    psi = Z[:, 0] * np.sign(Z[:, 0].sum())
+    occ = oracle_mod.occupations(om, ref["states"], psi)
+    b = pdg.Basis.truncated(om, n, eps, V, limit, 10**8, index=index)
+    for start in ("e1", "hf", "random"):
+        r = pdg.lanczos_ground(b, eps, V, krylov=30, tol=1e-11, start=start)
+        assert r.converged and abs(r.E0 - w[0]) <= 1e-10 * abs(w[0]), start
+        np.testing.assert_allclose(r.occ, occ, atol=1e-8)
+        np.testing.assert_allclose(r.psi.cpu().numpy(), psi, atol=1e-7)
+    m = pdg.lanczos_ground(b, eps, V, krylov=30, tol=1e-10, start="random", precision="f32")
+    assert m.converged and m.iterations_f32 > 0 and abs(m.E0 - w[0]) <= 1e-9 * abs(w[0])
+    assert r.E0 >= np.linalg.eigvalsh(H)[0] - 1e-10
+
+
+def test_ground_state_larger_vs_oracle_lanczos(pdg, oracle_mod):
+    # C(24, 12) = 2.7e6 states truncated to 2e5 with the paper's 1e8 bins;
+    # many tiles and a ragged last one.
+    om, n, limit = 24, 12, 200000
+    _, _, eps, V = inputs.c5_instance(om, n, seed=9)
+    print("trunc ground om=24 n=12", flush=True)
+    ref_sel = oracle_mod.trunc_select(om, n, eps, V, limit, 10**8)
+    b = pdg.Basis.truncated(om, n, eps, V, limit, 10**8)
+    _check_select(b.trunc_info, ref_sel)
+    r = pdg.lanczos_ground(b, eps, V, krylov=30, tol=1e-10, start="random", seed=3)
+    ref = oracle_mod.lanczos_ground(om, n, eps, V, krylov=30, tol=1e-10, basis=ref_sel["states"],
+                                    index_mode="bsearch_truncated")
+    assert r.converged and abs(r.E0 - ref["E0"]) <= 2e-10 * abs(ref["E0"])
+    np.testing.assert_allclose(r.occ, ref["occ"], atol=1e-7)
+    # fewer states, higher energy: the full-space ground state lies below
+    full = pdg.lanczos_ground(pdg.Basis(om, n, store_states=False), eps, V, krylov=30, tol=1e-10, want_psi=False)
+    assert full.E0 < r.E0
+
+
+def test_truncated_handle_errors(pdg):
+    import torch
+    om, n = 12, 6
+    _, _, eps, V = inputs.c5_instance(om, n, seed=1)
+    info = pdg.trunc_select(om, n, eps, V, 100, 1000)
+    with pytest.raises(pdg.PairDiagError):   # different couplings than the selection
+        pdg.Basis.truncated(om, n, eps, V * 1.5, 100, 1000, info=info)
+    bad = pdg.TruncInfo.from_buffer_copy(info)
+    bad.kept = info.kept - 5   # no longer the count of the cut: rejected, nothing written past the buffer
+    with pytest.raises(pdg.PairDiagError):
+        pdg.Basis.truncated(om, n, eps, V, 100, 1000, info=bad)
+    b = pdg.Basis.truncated(om, n, eps, V, 100, 1000, info=info)
+    with pytest.raises(pdg.PairDiagError):
+        b.rank(torch.zeros(4, dtype=torch.int64, device="cuda"))
+    with pytest.raises(pdg.PairDiagError):
+        b.warm_start(torch.zeros(om))
+    with pytest.raises(pdg.PairDiagError):
+        pdg.trunc_select(om, n, eps, V, 0, 1000)
