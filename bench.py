@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-warm", action="store_true", help="skip the learned-warm-start time-to-E0 solve")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-instance batched solve")
     ap.add_argument("--no-odd", action="store_true", help="skip the odd-system (all blocks) solve")
+    ap.add_argument("--no-trunc", action="store_true", help="skip the truncated-space leg")
     ap.add_argument("--no-starts", action="store_true", help="skip the E1 and HF start solves (context)")
     ap.add_argument("--no-prev", action="store_true",
                     help="skip the previous-solution start (couplings x1.01 from the converged state)")
@@ -319,6 +320,47 @@ def main():
         log(f"batched: {batched['converged']}/{args.batched_count} converged in {batched['seconds']:.2f} s, "
             f"{batched['nnz_per_s']:.3e} nnz/s")
 
+    # Truncated space (Sec. 3.5): the same Omega=32 instance cut to 1e8 states
+    # with the paper's 1e8 histogram bins; products with both rank-to-row maps.
+    trunc = None
+    if not args.no_trunc:
+        tl, tb = 100_000_000, 10**8
+        pairdiag.trunc_select(om, n, eps, V, tl, tb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tinfo = pairdiag.trunc_select(om, n, eps, V, tl, tb)
+        t1 = time.perf_counter()
+        tbas = pairdiag.Basis.truncated(om, n, eps, V, tl, tb, info=tinfo)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tms = {}
+        for index in ("bitmap", "bsearch"):
+            tb_i = tbas if index == "bitmap" else pairdiag.Basis.truncated(om, n, eps, V, tl, tb, index=index,
+                                                                          info=tinfo)
+            for dt in (torch.float32, torch.float64):
+                xt = torch.ones(tb_i.dim, dtype=dt, device="cuda")
+                yt = tb_i.sigma(eps, V, xt)
+                reps = 5 if index == "bitmap" else 2
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    tb_i.sigma(eps, V, xt, yt)
+                e1.record()
+                torch.cuda.synchronize()
+                tms[f"{index}_{'f32' if dt == torch.float32 else 'f64'}_ms"] = e0.elapsed_time(e1) / reps
+                del xt, yt
+            del tb_i
+        tg = pairdiag.lanczos_ground(tbas, eps, V, krylov=args.krylov, tol=args.tol, start="random", seed=1,
+                                     precision="f32", want_psi=False)
+        trunc = dict(workload=f"Omega={om}, n={n} truncated to <= {tl} states, {tb} bins", kept=int(tinfo.kept),
+                     cut_bin=int(tinfo.cut_bin), cutoff=tinfo.cutoff, select_seconds=t1 - t0,
+                     build_seconds=t2 - t1, sigma=tms, solve_seconds=tg.seconds, products=tg.iterations,
+                     E0=tg.E0, E0_minus_full=tg.E0 - mixed.E0, converged=tg.converged)
+        log(f"truncated: kept {tinfo.kept}, select {t1 - t0:.3f} s, build {t2 - t1:.3f} s, sigma {tms}, "
+            f"solve {tg.iterations} products {tg.seconds:.2f} s")
+        del tbas
+        torch.cuda.empty_cache()
+
     # Odd particle number (blocking): every block of an omega = 25, 12-pair
     # instance (2n + 1 = 25 particles), each block 12 pairs on 24 orbits.
     odd = None
@@ -397,6 +439,7 @@ def main():
         "basis_create_seconds": basis_seconds,
         "batched": batched,
         "odd": odd,
+        "truncated": trunc,
         "sigma": sig,
     }
     print(json.dumps(out), flush=True)
