@@ -11,6 +11,8 @@ Functions and the passages they follow:
   dense_ground                                            E0 as the lowest eigenvalue of the explicit H
   lanczos_ground                                          Sec. 3.4, Alg. lanczos, full reorthogonalisation,
                                                           restart with the ground Ritz vector, Eq. convergence
+  lowest_eigenpairs                                       the first few states (Sec. 3.4): lowest eigenpairs of H
+                                                          by a library eigensolver (dense, or ARPACK on sigma)
   occupations, monopole_min                               Sec. 4.3 outputs N_Occup and Monopole_Min
   blocked_instance, odd_ground                            Sec. 2 Eq. hamiltonian3 (blocking), Sec. 4.2 Block, Sec. 4.3 N_Occup
   diagonals, trunc_select, sigma(index_mode=              Sec. 3.5 truncation (diagonal histogram, cut, binary
@@ -293,6 +295,28 @@ def lanczos_ground(omega: int, n: int, eps, V, krylov: int = 50, tol: float = 1e
             return _finish(omega, basis, psi, t @ r, iterations, cycle, residual)
         p = psi
     return _finish(omega, basis, psi, theta, iterations, max_restarts, residual)
+
+
+def lowest_eigenpairs(omega: int, n: int, eps, V, nev: int, dense_limit: int = 6000):
+    """The nev lowest eigenvalues of H with eigenvectors (normalised, sum >= 0)
+    and their N_Occup: the definition, by a library eigensolver -- dense eigh
+    up to dense_limit states, otherwise ARPACK (scipy eigsh, smallest
+    algebraic) on a linear operator that applies the oracle's own product."""
+    eps, V = _check_h(omega, eps, V)
+    basis = basis_alg1(omega, n)
+    d = basis.size
+    if d <= dense_limit:
+        w, Z = np.linalg.eigh(dense_h(omega, n, eps, V, basis))
+        w, Z = w[:nev], Z[:, :nev]
+    else:
+        from scipy.sparse.linalg import LinearOperator, eigsh
+        op = LinearOperator((d, d), matvec=lambda v: sigma(omega, n, eps, V, basis, np.ravel(v)), dtype=np.float64)
+        w, Z = eigsh(op, k=nev, which="SA", tol=1e-13, v0=np.ones(d), ncv=max(2 * nev + 20, 40))
+        order = np.argsort(w)
+        w, Z = w[order], Z[:, order]
+    Z = np.stack([_normalise_sign(Z[:, i]) for i in range(nev)], axis=1)
+    occ = np.stack([occupations(omega, basis, Z[:, i]) for i in range(nev)])
+    return w, Z, occ
 
 
 def _finish(omega, basis, psi, theta, iterations, restarts, residual):
