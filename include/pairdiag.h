@@ -223,6 +223,31 @@ pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V,
                             const double *x0_dev, double *E0, double *psi0_dev, double *occ,
                             pd_lanczos_info *info, hipStream_t stream);
 
+/* The nev lowest eigenpairs (the paper's "first few states", Sec. 3.4) by
+ * thick-restart Lanczos, FP64: each cycle extends the kept Ritz vectors by
+ * Krylov steps (the step of pd_lanczos_ground: recurrence subtracted, one
+ * Gram-Schmidt pass against all stored vectors, a second on the DGKS or
+ * rounding test) up to krylov vectors; the restart keeps the
+ * min(krylov - 1, nev + (krylov - nev) / 2) lowest Ritz vectors and the
+ * residual direction.  Stops when every wanted Ritz residual estimate is
+ * <= tol; each returned pair is then checked with an explicit FP64 product:
+ * E[i] is its Rayleigh quotient and residuals[i] = ||H u - E u|| / |E|.
+ * Options: krylov >= nev + 2 (unless krylov >= dim), tol, max_restarts,
+ * mode 1 = one cycle, start PD_START_E1 or PD_START_RANDOM (seed),
+ * precision PD_F64.  A start vector's Krylov space holds one vector per
+ * distinct eigenvalue: an exactly degenerate level appears once.
+ * Outputs: E (host, nev doubles, ascending); psi_dev (optional, device,
+ * nev x dim doubles, state i at psi_dev + i * dim, normalised, sum >= 0);
+ * occ (optional, host, nev x omega); residuals (optional, host, nev);
+ * info (iterations = products including the checks, restarts = cycles,
+ * residual = the largest explicit residual).  Returns PD_ENOCONV (outputs
+ * filled; NaN for pairs the Krylov space did not contain) if a pair misses
+ * the tolerance.  Works on truncated handles.  Synchronises `stream`. */
+size_t pd_lanczos_eigs_workspace_bytes(pd_basis b, int nev, const pd_lanczos_opts *o);
+pd_status pd_lanczos_eigs(pd_basis b, const double *eps, const double *V, int nev, const pd_lanczos_opts *o,
+                          void *work_dev, size_t work_bytes, double *E, double *psi_dev, double *occ,
+                          double *residuals, pd_lanczos_info *info, hipStream_t stream);
+
 /* <N_i> = 2 sum_k psi_k^2 [orbit i occupied in state k] for a device vector
  * psi (dim doubles, not renormalised); occ_host receives omega doubles.
  * work_dev needs pd_occupations_workspace_bytes(b).  Synchronises `stream`. */

@@ -68,6 +68,10 @@ pd_status pack_coefficients(int omega, int n, const double *eps, const double *V
 }
 
 size_t lanczos_workspace_bytes(int64_t dim, const pd_lanczos_opts *o);
+size_t lanczos_eigs_workspace_bytes(int64_t dim, const pd_lanczos_opts *o);
+pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, const pd_lanczos_opts *o, void *work,
+                           size_t work_bytes, double *E_out, double *psi, double *occ_out, double *res_out,
+                           pd_lanczos_info *info_out, hipStream_t s);
 pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_opts *o, void *work,
                       size_t work_bytes, const double *x0, double *E0_out, double *psi0, double *occ_out,
                       pd_lanczos_info *info_out, hipStream_t s);
@@ -557,6 +561,34 @@ pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V, cons
         if (overlap(psi0_dev, b->dim * 8, work_dev, work_bytes)) return fail(PD_EINVAL, "psi0 overlaps workspace");
     }
     return lanczos_run(b, blk, o, work_dev, work_bytes, x0_dev, E0, psi0_dev, occ, info, stream);
+}
+
+size_t pd_lanczos_eigs_workspace_bytes(pd_basis b, int nev, const pd_lanczos_opts *o) {
+    if (!b || nev < 1 || check_opts(o) != PD_OK) return 0;
+    return lanczos_eigs_workspace_bytes(b->dim, o);
+}
+
+pd_status pd_lanczos_eigs(pd_basis b, const double *eps, const double *V, int nev, const pd_lanczos_opts *o,
+                          void *work_dev, size_t work_bytes, double *E, double *psi_dev, double *occ,
+                          double *residuals, pd_lanczos_info *info, hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if ((st = check_opts(o)) != PD_OK) return st;
+    if (!E) return fail(PD_EINVAL, "E is NULL");
+    if (nev < 1 || nev > b->dim) return fail(PD_EINVAL, "nev=%d outside [1, dim=%lld]", nev, (long long)b->dim);
+    if ((st = check_sigma_range(b)) != PD_OK) return st;
+    CoefBlock blk;
+    if ((st = pack_coefficients(b->omega, b->n, eps, V, &blk)) != PD_OK) return st;
+    size_t need = lanczos_eigs_workspace_bytes(b->dim, o);
+    if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+    if ((st = check_device_ptr(work_dev, "work_dev", need)) != PD_OK) return st;
+    if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
+    if (psi_dev) {
+        const size_t pb = (size_t)nev * (size_t)b->dim * 8;
+        if ((st = check_device_ptr(psi_dev, "psi_dev", pb)) != PD_OK) return st;
+        if (overlap(psi_dev, pb, work_dev, work_bytes)) return fail(PD_EINVAL, "psi_dev overlaps workspace");
+    }
+    return lanczos_eigs_run(b, blk, nev, o, work_dev, work_bytes, E, psi_dev, occ, residuals, info, stream);
 }
 
 size_t pd_occupations_workspace_bytes(pd_basis b) {

@@ -145,6 +145,10 @@ hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t di
 struct SmallVec {
     double v[64];
 };
+// Thick restart, in place: Q[o] = sum_{j < ncols} Y_dev[j * k + o] Q[j] for o < k, then
+// Q[k] = zs * Q[zcol] if zcol >= 0 (zcol >= k).  Y_dev: device, ncols x k row-major.
+hipError_t launch_combine_many(double *Q, int64_t ld, int ncols, int k, int64_t dim, const double *Y_dev, int zcol,
+                               double zs, hipStream_t s);
 // out = sum_j y[j] Q[j] (j < ncols, y on the host); nrm2_dev[0] = ||out||^2, sum_dev[0] = sum(out).
 hipError_t launch_combine(const double *Q, int64_t ld, int ncols, int64_t dim, const double *y_host,
                           double *out, double *partials, double *nrm2_dev, double *sum_dev,

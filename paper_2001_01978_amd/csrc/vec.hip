@@ -209,6 +209,32 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const double *__restr
     block_partials<2>(acc, 2, sh, partials);
 }
 
+// Thick restart, in place and row by row: Q[o] = sum_{j < ncols} Y[j * k + o] Q[j]
+// for o < k, and Q[k] = zs * Q[zcol] when zcol >= 0.  Each thread reads all
+// ncols (+1) entries of its row before writing any, so no other row is read.
+template <int KMAX>
+__global__ __launch_bounds__(kThreads) void combine_many_kernel(double *__restrict__ Q, int64_t ld, int ncols,
+                                                                int k, int64_t dim, const double *__restrict__ Y,
+                                                                int zcol, double zs) {
+    __shared__ double Ys[kMaxCols * kMaxCols];
+    for (int t = threadIdx.x; t < KMAX * k; t += kThreads) Ys[t] = t < ncols * k ? Y[t] : 0.0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
+        double q[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) q[j] = j < ncols ? Q[(size_t)j * ld + i] : 0.0;
+        const double z = zcol >= 0 ? Q[(size_t)zcol * ld + i] : 0.0;
+        for (int o = 0; o < k; ++o) {
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) v += Ys[j * k + o] * q[j];
+            Q[(size_t)o * ld + i] = v;
+        }
+        if (zcol >= 0) Q[(size_t)k * ld + i] = zs * z;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void norm_sum_kernel(const double *__restrict__ x, int64_t dim,
                                                             double *__restrict__ partials) {
     __shared__ double sh[kWaves * 2];
@@ -413,6 +439,16 @@ hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t di
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize(partials, nb, 1, 1.0, nrm2_dev, s);
+}
+
+hipError_t launch_combine_many(double *Q, int64_t ld, int ncols, int k, int64_t dim, const double *Y_dev, int zcol,
+                               double zs, hipStream_t s) {
+    if (ncols < 1 || ncols > kMaxCols || k < 1 || k > kMaxCols || zcol > kMaxCols || (zcol >= 0 && zcol < k))
+        return hipErrorInvalidValue;
+    const unsigned nb = grid_for(dim);
+    PD_DISPATCH_COLS(ncols, combine_many_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, k, dim, Y_dev, zcol,
+                     zs);
+    return hipGetLastError();
 }
 
 hipError_t launch_combine(const double *Q, int64_t ld, int ncols, int64_t dim, const double *y_host, double *out,

@@ -86,6 +86,9 @@ SIGNATURES = {
     "pd_lanczos_workspace_bytes": (SZ, [P, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_ground": (I, [P, P, P, ctypes.POINTER(LanczosOpts), P, SZ, P, ctypes.POINTER(D), P, P,
                               ctypes.POINTER(LanczosInfo), P]),
+    "pd_lanczos_eigs_workspace_bytes": (SZ, [P, I, ctypes.POINTER(LanczosOpts)]),
+    "pd_lanczos_eigs": (I, [P, P, P, I, ctypes.POINTER(LanczosOpts), P, SZ, P, P, P, P, ctypes.POINTER(LanczosInfo),
+                            P]),
     "pd_occupations_workspace_bytes": (SZ, [P]),
     "pd_occupations": (I, [P, P, P, SZ, P, P]),
     "pd_tridiag_lowest": (I, [I, P, P, ctypes.POINTER(D), P]),
@@ -404,6 +407,48 @@ def lanczos_ground(basis: Basis, eps, V, x0=None, want_psi=True, workspace=None,
                        sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32,
                        fallback_used=bool(info.fallback_used), status=st,
                        reorth_second_passes=info.reorth_second_passes)
+
+
+@dataclass
+class Eigenpairs:
+    E: np.ndarray
+    psi: object
+    occ: np.ndarray
+    residuals: np.ndarray
+    iterations: int
+    restarts: int
+    converged: bool
+    seconds: float
+    status: int
+
+
+def lanczos_eigs(basis: Basis, eps, V, nev: int, want_psi=True, workspace=None, stream=None, **kw) -> Eigenpairs:
+    """The nev lowest eigenpairs by thick-restart Lanczos (pd_lanczos_eigs)."""
+    torch = _torch()
+    L = load()
+    kw.setdefault("start", "random")
+    o = make_opts(**kw)
+    eps = _host_f64(eps, (basis.omega,))
+    V = _host_f64(V, (basis.omega, basis.omega))
+    nb = L.pd_lanczos_eigs_workspace_bytes(basis.handle, nev, ctypes.byref(o))
+    if nb == 0:
+        raise PairDiagError(PD_EINVAL, "bad options")
+    if workspace is None:
+        buf, off = device_buffer(nb, basis.device)
+    else:
+        buf, off = workspace
+    psi = torch.empty((nev, basis.dim), dtype=torch.float64, device=basis.device) if want_psi else None
+    E = np.empty(nev)
+    occ = np.empty((nev, basis.omega))
+    res = np.empty(nev)
+    info = LanczosInfo()
+    st = L.pd_lanczos_eigs(basis.handle, _hp(eps), _hp(V), nev, ctypes.byref(o),
+                           ctypes.c_void_p(buf.data_ptr() + off), nb, _hp(E),
+                           _dptr(psi) if psi is not None else None, _hp(occ), _hp(res), ctypes.byref(info),
+                           _stream(stream))
+    _check(st, allow=(PD_ENOCONV,))
+    return Eigenpairs(E=E, psi=psi, occ=occ, residuals=res, iterations=info.iterations, restarts=info.restarts,
+                      converged=bool(info.converged), seconds=info.seconds, status=st)
 
 
 @dataclass
