@@ -15,6 +15,8 @@ Functions and the passages they follow:
                                                           by a library eigensolver (dense, or ARPACK on sigma)
   occupations, monopole_min                               Sec. 4.3 outputs N_Occup and Monopole_Min
   blocked_instance, odd_ground                            Sec. 2 Eq. hamiltonian3 (blocking), Sec. 4.2 Block, Sec. 4.3 N_Occup
+  scf_ground                                              Sec. 1 and 6: the exact solution inside a self-consistent
+                                                          loop (synthetic mean field eps0 + W <N>/2, linear mixing)
   diagonals, trunc_select, sigma(index_mode=              Sec. 3.5 truncation (diagonal histogram, cut, binary
     'bsearch_truncated')                                  search in the truncated basis)
   richardson_evb                                          constant-G check (Richardson equations, eigenvalue form)
@@ -371,6 +373,29 @@ def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8):
     keep = b <= cut
     return dict(full_dim=full, kept=int(keep.sum()), cut_bin=cut, dmin=dmin, dmax=dmax, scale=scale,
                 states=basis[keep], ranks=np.nonzero(keep)[0])
+
+
+# ---------------------------------------------------------------- self-consistent loop (Sec. 1, Sec. 6)
+
+def scf_ground(omega: int, n: int, eps0, W, V, mixing: float = 0.5, tol: float = 1e-10, max_iter: int = 200):
+    """The exact pairing solution inside a self-consistent mean-field loop, the
+    use the paper names for it in place of BCS.  The mean field is synthetic:
+    eps_i = eps0_i + sum_j W_ij <N_j> / 2.  Iteration t solves the pairing
+    ground state with eps^(t) (dense), forms eps_new = eps0 + W occ / 2, stops
+    when max |eps_new - eps^(t)| <= tol, else mixes
+    eps^(t+1) = (1 - mixing) eps^(t) + mixing eps_new.
+    Returns dict(eps, occ, E0, iterations, change) for the last solve."""
+    eps0, V = _check_h(omega, eps0, V)
+    W = _f64(W)
+    eps = eps0.copy()
+    for it in range(1, max_iter + 1):
+        E0, _, occ, _ = dense_ground(omega, n, eps, V)
+        new = eps0 + W @ occ / 2.0
+        change = float(np.max(np.abs(new - eps)))
+        if change <= tol:
+            return dict(eps=eps, occ=occ, E0=E0, iterations=it, change=change)
+        eps = (1.0 - mixing) * eps + mixing * new
+    return dict(eps=eps, occ=occ, E0=E0, iterations=max_iter, change=change)
 
 
 # ---------------------------------------------------------------- odd mass (Sec. 2, Eq. hamiltonian3)
