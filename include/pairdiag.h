@@ -248,6 +248,41 @@ pd_status pd_lanczos_eigs(pd_basis b, const double *eps, const double *V, int ne
                           void *work_dev, size_t work_bytes, double *E, double *psi_dev, double *occ,
                           double *residuals, pd_lanczos_info *info, hipStream_t stream);
 
+/* The exact pairing solution inside a self-consistent mean-field loop, the
+ * use the paper names for it in place of BCS (Sec. 1, Sec. 6).  The mean
+ * field is synthetic: eps_i = eps0_i + sum_j W_ij <N_j> / 2 (W host,
+ * omega x omega row-major, finite).  Iteration t solves the ground state of
+ * Eq. hamiltonian2 with eps^(t) and V (pd_lanczos_ground with o; from the
+ * second iteration on, with reuse_psi, started from the previous ground state),
+ * forms eps_new = eps0 + W <N> / 2 and stops when max |eps_new - eps^(t)| <= tol,
+ * else eps^(t+1) = (1 - mixing) eps^(t) + mixing eps_new.
+ * o->start: E1, HF or RANDOM (the first solve).  work_dev: device, 256-byte
+ * aligned, pd_scf_workspace_bytes(b, o) bytes.  Outputs (host): eps_out (the
+ * eps of the last solve), occ_out (its <N_i>), *E0 (its ground-state energy);
+ * psi0_dev (optional, device, dim doubles) its ground state; info.
+ * Returns PD_ENOCONV (outputs filled) if max_iter is reached first.
+ * Synchronises `stream`. */
+typedef struct {
+    int max_iter;     /* iterations (solves) at most */
+    double tol;       /* on max |eps_new - eps| */
+    double mixing;    /* in (0, 1] */
+    int reuse_psi;    /* 1: start every solve after the first from the previous ground state */
+} pd_scf_opts;
+typedef struct {
+    int iterations;         /* solves */
+    int converged;          /* 1 if the field change met tol */
+    int products;           /* H q products over all solves */
+    int products_first;     /* of the first solve */
+    int lanczos_converged;  /* 1 if every solve met o->tol */
+    double change;          /* max |eps_new - eps| of the last iteration */
+    double last_residual;   /* rho of the last solve */
+    double seconds;
+} pd_scf_info;
+size_t pd_scf_workspace_bytes(pd_basis b, const pd_lanczos_opts *o);
+pd_status pd_scf_ground(pd_basis b, const double *eps0, const double *W, const double *V, const pd_scf_opts *so,
+                        const pd_lanczos_opts *o, void *work_dev, size_t work_bytes, double *eps_out,
+                        double *occ_out, double *E0, double *psi0_dev, pd_scf_info *info, hipStream_t stream);
+
 /* <N_i> = 2 sum_k psi_k^2 [orbit i occupied in state k] for a device vector
  * psi (dim doubles, not renormalised); occ_host receives omega doubles.
  * work_dev needs pd_occupations_workspace_bytes(b).  Synchronises `stream`. */

@@ -57,6 +57,17 @@ class TruncInfo(ctypes.Structure):
                 ("dmax", ctypes.c_double), ("scale", ctypes.c_double), ("cutoff", ctypes.c_double)]
 
 
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("mixing", ctypes.c_double),
+                ("reuse_psi", ctypes.c_int)]
+
+
+class ScfInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("products", ctypes.c_int),
+                ("products_first", ctypes.c_int), ("lanczos_converged", ctypes.c_int), ("change", ctypes.c_double),
+                ("last_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 class MlpShape(ctypes.Structure):
     _fields_ = [("inp", ctypes.c_int), ("h1", ctypes.c_int), ("h2", ctypes.c_int), ("out", ctypes.c_int)]
 
@@ -89,6 +100,9 @@ SIGNATURES = {
     "pd_lanczos_eigs_workspace_bytes": (SZ, [P, I, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_eigs": (I, [P, P, P, I, ctypes.POINTER(LanczosOpts), P, SZ, P, P, P, P, ctypes.POINTER(LanczosInfo),
                             P]),
+    "pd_scf_workspace_bytes": (SZ, [P, ctypes.POINTER(LanczosOpts)]),
+    "pd_scf_ground": (I, [P, P, P, P, ctypes.POINTER(ScfOpts), ctypes.POINTER(LanczosOpts), P, SZ, P, P,
+                          ctypes.POINTER(D), P, ctypes.POINTER(ScfInfo), P]),
     "pd_occupations_workspace_bytes": (SZ, [P]),
     "pd_occupations": (I, [P, P, P, SZ, P, P]),
     "pd_tridiag_lowest": (I, [I, P, P, ctypes.POINTER(D), P]),
@@ -449,6 +463,48 @@ def lanczos_eigs(basis: Basis, eps, V, nev: int, want_psi=True, workspace=None, 
     _check(st, allow=(PD_ENOCONV,))
     return Eigenpairs(E=E, psi=psi, occ=occ, residuals=res, iterations=info.iterations, restarts=info.restarts,
                       converged=bool(info.converged), seconds=info.seconds, status=st)
+
+
+@dataclass
+class ScfResult:
+    eps: np.ndarray
+    occ: np.ndarray
+    E0: float
+    psi: object
+    info: dict
+    status: int
+
+
+def scf_ground(basis: Basis, eps0, W, V, mixing=0.5, tol=1e-10, max_iter=200, reuse_psi=True, want_psi=False,
+               lanczos_tol=1e-12, workspace=None, stream=None, **kw) -> ScfResult:
+    """Ground state inside a self-consistent loop with the mean field eps0 + W <N>/2 (pd_scf_ground).
+    tol: on the field change; lanczos_tol: of every solve."""
+    torch = _torch()
+    L = load()
+    o = make_opts(tol=lanczos_tol, **kw)
+    so = ScfOpts(max_iter=max_iter, tol=tol, mixing=mixing, reuse_psi=int(reuse_psi))
+    om = basis.omega
+    eps0 = _host_f64(eps0, (om,))
+    W = _host_f64(W, (om, om))
+    V = _host_f64(V, (om, om))
+    nb = L.pd_scf_workspace_bytes(basis.handle, ctypes.byref(o))
+    if nb == 0:
+        raise PairDiagError(PD_EINVAL, "bad options")
+    if workspace is None:
+        buf, off = device_buffer(nb, basis.device)
+    else:
+        buf, off = workspace
+    psi = torch.empty(basis.dim, dtype=torch.float64, device=basis.device) if want_psi else None
+    eps = np.empty(om)
+    occ = np.empty(om)
+    e0 = ctypes.c_double()
+    info = ScfInfo()
+    st = L.pd_scf_ground(basis.handle, _hp(eps0), _hp(W), _hp(V), ctypes.byref(so), ctypes.byref(o),
+                         ctypes.c_void_p(buf.data_ptr() + off), nb, _hp(eps), _hp(occ), ctypes.byref(e0),
+                         _dptr(psi) if psi is not None else None, ctypes.byref(info), _stream(stream))
+    _check(st, allow=(PD_ENOCONV,))
+    return ScfResult(eps=eps, occ=occ, E0=e0.value, psi=psi, info={k: getattr(info, k) for k, _ in ScfInfo._fields_},
+                     status=st)
 
 
 @dataclass
