@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-odd", action="store_true", help="skip the odd-system (all blocks) solve")
     ap.add_argument("--no-trunc", action="store_true", help="skip the truncated-space leg")
     ap.add_argument("--no-eigs", action="store_true", help="skip the lowest-eigenpairs (thick restart) leg")
+    ap.add_argument("--no-scf", action="store_true", help="skip the self-consistent loop leg")
     ap.add_argument("--no-starts", action="store_true", help="skip the E1 and HF start solves (context)")
     ap.add_argument("--no-prev", action="store_true",
                     help="skip the previous-solution start (couplings x1.01 from the converged state)")
@@ -378,6 +379,27 @@ def main():
         del tbas
         torch.cuda.empty_cache()
 
+    # Self-consistent loop (synthetic mean field eps0 + W <N>/2) on an Omega=24,
+    # 12-pair instance, with and without the previous-solution start.
+    scf = None
+    if not args.no_scf:
+        so, sn = 24, 12
+        _, _, seps, sV = inputs.c5_instance(so, sn, seed=0)
+        u = inputs.uniform01(5, 0, so * so).reshape(so, so)
+        sW = 0.3 * 0.5 * (u + u.T)
+        sb = pairdiag.Basis(so, sn, store_states=False)
+        scf = dict(workload=f"Omega={so}, n={sn}, W = 0.3 (U + U^T)/2, mixing 0.6, field tol 1e-8, "
+                            f"solve tol 1e-11, krylov 20")
+        for reuse in (True, False):
+            rs = pairdiag.scf_ground(sb, seps, sW, sV, mixing=0.6, tol=1e-8, krylov=20, start="random",
+                                     reuse_psi=reuse, lanczos_tol=1e-11)
+            scf["previous_solution_start" if reuse else "random_start_each"] = dict(
+                iterations=rs.info["iterations"], products=rs.info["products"], seconds=rs.info["seconds"],
+                converged=bool(rs.info["converged"]), E0=rs.E0)
+        log(f"scf: {scf['previous_solution_start']['products']} products {scf['previous_solution_start']['seconds']:.2f} s "
+            f"vs {scf['random_start_each']['products']} / {scf['random_start_each']['seconds']:.2f} s")
+        del sb
+
     # Odd particle number (blocking): every block of an omega = 25, 12-pair
     # instance (2n + 1 = 25 particles), each block 12 pairs on 24 orbits.
     odd = None
@@ -458,6 +480,7 @@ def main():
         "odd": odd,
         "truncated": trunc,
         "eigenpairs": eigs,
+        "scf": scf,
         "sigma": sig,
     }
     print(json.dumps(out), flush=True)
