@@ -18,7 +18,8 @@ Functions and the passages they follow:
   scf_ground                                              Sec. 1 and 6: the exact solution inside a self-consistent
                                                           loop (synthetic mean field eps0 + W <N>/2, linear mixing)
   diagonals, trunc_select, sigma(index_mode=              Sec. 3.5 truncation (diagonal histogram, cut, binary
-    'bsearch_truncated')                                  search in the truncated basis)
+    'bsearch_truncated'), trunc_bits,                     search in the truncated basis; C histogram, kept bits and
+    trunc_sigma_sampled                                   sampled rows for spaces too large to store)
   richardson_evb                                          constant-G check (Richardson equations, eigenvalue form)
   pbcs_vector                                             number-projected product start vector (warm start)
   mlp_*                                                   FP64 reference of the warm-start network
@@ -47,7 +48,7 @@ def build(force: bool = True) -> str:
     """Compile pd_oracle.c with gcc (OpenMP over rows)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -71,6 +72,11 @@ def lib():
         L.or_sigma_sampled.restype = i32
         L.or_sigma_sampled.argtypes = [i32, i32, P, P, i64, P, P, i64, P]
         L.or_dense_h.restype, L.or_dense_h.argtypes = i32, [i32, i32, P, P, P, i64, P]
+        L.or_trunc_count.restype = i32
+        L.or_trunc_count.argtypes = [i32, i32, P, dbl, dbl, i64, i32, i64, i64, P]
+        L.or_trunc_bits.restype, L.or_trunc_bits.argtypes = i32, [i32, i32, P, dbl, dbl, i64, i64, P]
+        L.or_trunc_sigma_sampled.restype = i32
+        L.or_trunc_sigma_sampled.argtypes = [i32, i32, P, P, P, P, P, i64, P, P]
         L.or_sigma_block.restype = i32
         L.or_sigma_block.argtypes = [i32, i32, P, P, i64, P, i64, i64, P]
         L.or_row_terms.restype = dbl
@@ -341,7 +347,7 @@ def diagonals(omega: int, eps, V, basis: np.ndarray) -> np.ndarray:
     return acc
 
 
-def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8):
+def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8, method: str = "auto"):
     """The truncation of Sec. 3.5.  If C(omega, n) exceeds `limit`, the
     diagonal elements are counted in `bins` equal bins from the smallest to the
     largest diagonal (Monopole_Min to Monopole_Max), the bins are accumulated
@@ -349,6 +355,8 @@ def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8):
     running count is still within the limit are kept (bin 0 in any case).
     The extreme diagonals are those of the n orbits with the smallest and the
     largest pair energy (stable order of 2 eps_i + V_ii).
+    method: 'numpy' (stored basis, vectorised), 'c' (bins counted by rank in C,
+    for spaces too large to store; states and ranks are then None) or 'auto'.
     Returns dict(full_dim, kept, cut_bin, dmin, dmax, scale, states, ranks)."""
     eps, V = _check_h(omega, eps, V)
     full = binom(omega, n)
@@ -362,6 +370,35 @@ def trunc_select(omega: int, n: int, eps, V, limit: int, bins: int = 10**8):
     dmin = extreme(order[:n])
     dmax = extreme(order[omega - n:])
     scale = bins / (dmax - dmin) if dmax > dmin else 0.0
+    if method == "c" or (method == "auto" and full > 4_000_000):
+        if full <= limit:
+            return dict(full_dim=full, kept=full, cut_bin=bins - 1, dmin=dmin, dmax=dmax, scale=scale,
+                        states=None, ranks=None)
+        dd = np.zeros(62)
+        dd[:omega] = d
+        # The running count in two levels: chunks of 4096 bins, then the bins
+        # of the chunk in which it first exceeds the limit.
+        def count(shift, lo, length):
+            out = np.zeros(length, dtype=np.uint64)
+            if lib().or_trunc_count(omega, n, _p(dd), dmin, scale, bins, shift, lo, length,
+                                    out.ctypes.data_as(ctypes.c_void_p)) != 0:
+                raise RuntimeError("bad count range")
+            return out.astype(np.int64)
+        nchunks = (bins + 4095) // 4096
+        coarse = np.concatenate([count(12, lo, min(65536, nchunks - lo)) for lo in range(0, nchunks, 65536)])
+        ccum = np.cumsum(coarse)
+        c = int(np.searchsorted(ccum, limit, side="right"))   # first chunk whose running count exceeds limit
+        base = int(ccum[c - 1]) if c > 0 else 0
+        fine_cum = base + np.cumsum(count(0, c * 4096, min(4096, bins - c * 4096)))
+        k = int(np.searchsorted(fine_cum, limit, side="right")) - 1
+        if k >= 0:
+            cut, kept = c * 4096 + k, int(fine_cum[k])
+        elif c > 0:
+            cut, kept = c * 4096 - 1, base
+        else:
+            cut, kept = 0, int(fine_cum[0])
+        return dict(full_dim=full, kept=kept, cut_bin=cut, dmin=dmin, dmax=dmax, scale=scale,
+                    states=None, ranks=None)
     basis = basis_alg1(omega, n)
     if full <= limit:
         return dict(full_dim=full, kept=full, cut_bin=bins - 1, dmin=dmin, dmax=dmax, scale=scale,
@@ -396,6 +433,36 @@ def scf_ground(omega: int, n: int, eps0, W, V, mixing: float = 0.5, tol: float =
             return dict(eps=eps, occ=occ, E0=E0, iterations=it, change=change)
         eps = (1.0 - mixing) * eps + mixing * new
     return dict(eps=eps, occ=occ, E0=E0, iterations=max_iter, change=change)
+
+
+def trunc_bits(omega: int, n: int, eps, V, sel, bins: int = 10**8):
+    """Kept-state bits of a selection from trunc_select (one uint64 per 64
+    full ranks), recomputed state by state in C, and the exclusive prefix
+    count of kept states per word."""
+    eps, V = _check_h(omega, eps, V)
+    d = np.zeros(62)
+    d[:omega] = 2.0 * eps + np.diag(V)
+    W = (sel["full_dim"] + 63) // 64
+    bits = np.zeros(W, dtype=np.uint64)
+    lib().or_trunc_bits(omega, n, _p(d), sel["dmin"], sel["scale"], bins, sel["cut_bin"],
+                        bits.ctypes.data_as(ctypes.c_void_p))
+    cnt = np.bitwise_count(bits).astype(np.int64)
+    prefix = np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.int64)
+    return bits, prefix
+
+
+def trunc_sigma_sampled(omega: int, n: int, eps, V, bits, prefix, ranks, x) -> np.ndarray:
+    """Rows of the truncated product (H restricted to the kept states) for the
+    listed kept full ranks, with targets located by the hash and the bits."""
+    eps, V = _check_h(omega, eps, V)
+    x = _f64(x)
+    ranks = np.ascontiguousarray(ranks, dtype=np.int64)
+    y = np.empty(ranks.size)
+    rc = lib().or_trunc_sigma_sampled(omega, n, _p(eps), _p(V), bits.ctypes.data_as(ctypes.c_void_p),
+                                      prefix.ctypes.data_as(ctypes.c_void_p), _p(ranks), ranks.size, _p(x), _p(y))
+    if rc != 0:
+        raise RuntimeError("a listed rank is not kept")
+    return y
 
 
 # ---------------------------------------------------------------- odd mass (Sec. 2, Eq. hamiltonian3)

@@ -20,6 +20,7 @@
  * used for parity.
  */
 #include <stdint.h>
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -290,6 +291,107 @@ void or_occupations(int omega, const uint64_t *basis, int64_t dim, const double 
         for (int i = 0; i < omega; ++i)
             if ((basis[k] >> i) & 1ull) occ[i] += 2.0 * w;
     }
+}
+
+/* ---------------------------------------------------------------- Sec. 3.5
+ * Bin of a state's diagonal element (Eq. diagonal, summed over the occupied
+ * orbits in ascending order) among `bins` equal bins starting at dmin. */
+static int64_t diag_bin(uint64_t s, const double *d, double dmin, double scale, int64_t bins)
+{
+    double acc = 0.0;
+    for (int q = 0; q < 62; ++q)
+        if ((s >> q) & 1ull) acc += d[q];
+    double v = floor((acc - dmin) * scale);
+    if (!(v > 0.0)) return 0;
+    if (v >= (double)(bins - 1)) return bins - 1;
+    return (int64_t)v;
+}
+
+/* Counts of the keys bin >> shift over the whole (omega, n) space, for keys in
+ * [lo, lo + len): out[key - lo] (len <= 65536).  Every 64 ranks start from the
+ * inverse hash and continue by '01' inversion; counts are per thread, then
+ * added. */
+int or_trunc_count(int omega, int n, const double *d, double dmin, double scale, int64_t bins, int shift,
+                   int64_t lo, int64_t len, uint64_t *out)
+{
+    if (len < 1 || len > 65536) return -1;
+    cmn_init();
+    const int64_t dim = (int64_t)or_binom(omega, n), W = (dim + 63) / 64;
+    memset(out, 0, (size_t)len * sizeof(uint64_t));
+#pragma omp parallel
+    {
+        uint64_t *mine = (uint64_t *)calloc((size_t)len, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t w = 0; w < W; ++w) {
+            const int64_t r0 = w * 64;
+            const int cnt = (int)(dim - r0 < 64 ? dim - r0 : 64);
+            uint64_t s = or_unhash(r0, n);
+            for (int j = 0; j < cnt; ++j) {
+                const int64_t key = diag_bin(s, d, dmin, scale, bins) >> shift;
+                if (key >= lo && key < lo + len) mine[key - lo]++;
+                if (j + 1 < cnt) s = or_next_state(s);
+            }
+        }
+#pragma omp critical
+        for (int64_t k = 0; k < len; ++k) out[k] += mine[k];
+        free(mine);
+    }
+    return 0;
+}
+
+/* bits[w] bit j = 1 iff the state of rank 64 w + j lies in a bin <= cut. */
+int or_trunc_bits(int omega, int n, const double *d, double dmin, double scale, int64_t bins, int64_t cut,
+                  uint64_t *bits)
+{
+    cmn_init();
+    const int64_t dim = (int64_t)or_binom(omega, n), W = (dim + 63) / 64;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t w = 0; w < W; ++w) {
+        const int64_t r0 = w * 64;
+        const int cnt = (int)(dim - r0 < 64 ? dim - r0 : 64);
+        uint64_t s = or_unhash(r0, n), m = 0;
+        for (int j = 0; j < cnt; ++j) {
+            if (diag_bin(s, d, dmin, scale, bins) <= cut) m |= 1ull << j;
+            if (j + 1 < cnt) s = or_next_state(s);
+        }
+        bits[w] = m;
+    }
+    return 0;
+}
+
+/* Rows of the truncated product for kept full ranks: the row's own index and
+ * a target's index are the kept ranks below them (bits plus the exclusive
+ * prefix count per word); targets outside the kept space are dropped.
+ * Returns -1 if a listed rank is not kept. */
+int or_trunc_sigma_sampled(int omega, int n, const double *eps, const double *V, const uint64_t *bits,
+                           const int64_t *prefix, const int64_t *ranks, int64_t count, const double *x, double *y)
+{
+    int bad = 0;
+    cmn_init();
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t r = ranks[q];
+        if (!((bits[r >> 6] >> (r & 63)) & 1ull)) { bad = 1; y[q] = 0.0; continue; }
+        const int64_t self = prefix[r >> 6] + __builtin_popcountll(bits[r >> 6] & ((1ull << (r & 63)) - 1ull));
+        const uint64_t s = or_unhash(r, n);
+        double diag = 0.0;
+        for (int i = 0; i < omega; ++i)
+            if ((s >> i) & 1ull) diag += 2.0 * eps[i] + V[i * omega + i];
+        double acc = diag * x[self];
+        for (int O = 0; O < omega; ++O) {
+            if (!((s >> O) & 1ull)) continue;
+            for (int E = 0; E < omega; ++E) {
+                if ((s >> E) & 1ull) continue;
+                const int64_t t = or_hash((s & ~(1ull << O)) | (1ull << E));
+                const uint64_t wd = bits[t >> 6];
+                if (!((wd >> (t & 63)) & 1ull)) continue;
+                acc += V[E * omega + O] * x[prefix[t >> 6] + __builtin_popcountll(wd & ((1ull << (t & 63)) - 1ull))];
+            }
+        }
+        y[q] = acc;
+    }
+    (void)n;
+    return bad ? -1 : 0;
 }
 
 int or_num_threads(void)

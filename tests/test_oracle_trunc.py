@@ -115,3 +115,36 @@ def test_truncated_ground_state_variational_and_nested(oracle_mod):
         assert r["E0"] == pytest.approx(E, abs=1e-9)
         assert r["occ"].sum() == pytest.approx(2 * n, abs=1e-9)
     assert prev == pytest.approx(E_full, abs=1e-12)
+
+
+@pytest.mark.parametrize("omega,n,limit,bins", [(14, 7, 1500, 10**8), (16, 6, 3000, 4096), (15, 10, 100, 7),
+                                                (18, 9, 20000, 10**6)])
+def test_c_histogram_path_matches_numpy_path(oracle_mod, omega, n, limit, bins):
+    eps, V = _inst(omega, omega + n)
+    a = oracle_mod.trunc_select(omega, n, eps, V, limit, bins, method="numpy")
+    c = oracle_mod.trunc_select(omega, n, eps, V, limit, bins, method="c")
+    for k in ("full_dim", "kept", "cut_bin", "dmin", "dmax", "scale"):
+        assert a[k] == c[k], k
+    bits, prefix = oracle_mod.trunc_bits(omega, n, eps, V, c, bins)
+    keep = np.unpackbits(bits.view(np.uint8), bitorder="little")[: a["full_dim"]].astype(bool)
+    np.testing.assert_array_equal(np.nonzero(keep)[0], a["ranks"])
+    x = np.random.default_rng(1).standard_normal(a["kept"])
+    rows = a["ranks"][:: max(1, a["kept"] // 300)]
+    y = oracle_mod.trunc_sigma_sampled(omega, n, eps, V, bits, prefix, rows, x)
+    y_all = oracle_mod.sigma(omega, n, eps, V, a["states"], x, index_mode="bsearch_truncated")
+    idx = np.searchsorted(a["ranks"], rows)
+    np.testing.assert_allclose(y, y_all[idx], rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("limit,bins", [(1, 10**8), (1, 5), (40, 4096), (700, 10**6), (2000, 9000)])
+def test_c_histogram_path_edges_with_ties(oracle_mod, limit, bins):
+    # coarse dyadic pair energies: many equal diagonals, so whole bins (and whole
+    # 4096-bin chunks) cross the limit at once
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_2001_01978_amd import inputs
+    omega, n = 16, 7
+    _, _, eps, V = inputs.dyadic_instance(omega, n, seed=4)
+    a = oracle_mod.trunc_select(omega, n, eps, V, limit, bins, method="numpy")
+    c = oracle_mod.trunc_select(omega, n, eps, V, limit, bins, method="c")
+    assert (a["kept"], a["cut_bin"]) == (c["kept"], c["cut_bin"])
