@@ -151,3 +151,39 @@ def test_truncated_handle_errors(pdg):
         b.warm_start(torch.zeros(om))
     with pytest.raises(pdg.PairDiagError):
         pdg.trunc_select(om, n, eps, V, 0, 1000)
+
+
+def test_full_size_cut_kept_set_and_sampled_rows(pdg, oracle_mod):
+    # The benchmark's truncated workload: Omega=32, n=16 (6.0e8 states) cut to at
+    # most 1e8 with 1e8 bins.  The cut bit-exact, the whole kept set bit-exact,
+    # and rows sampled from the oracle's kept set in FP64 and FP32.
+    import torch
+    om, n, limit, bins = 32, 16, 100_000_000, 10**8
+    _, _, eps, V = inputs.c5_instance(om, n, seed=0)
+    print("trunc full size: select", flush=True)
+    info = pdg.trunc_select(om, n, eps, V, limit, bins)
+    ref = oracle_mod.trunc_select(om, n, eps, V, limit, bins, method="c")
+    _check_select(info, ref)
+    print("trunc full size: kept set", flush=True)
+    bits, prefix = oracle_mod.trunc_bits(om, n, eps, V, ref, bins)
+    b = pdg.Basis.truncated(om, n, eps, V, limit, bins, info=info)
+    kr = b.kept_ranks().cpu().numpy()
+    assert kr.size == ref["kept"]
+    flags = np.zeros(bits.size * 64, dtype=bool)
+    flags[kr] = True
+    np.testing.assert_array_equal(np.packbits(flags, bitorder="little").view(np.uint64), bits)
+    del flags, kr
+    print("trunc full size: sampled rows", flush=True)
+    rng = np.random.default_rng(11)
+    cand = rng.integers(0, ref["full_dim"], 40000)
+    rows = np.unique(cand[((bits[cand >> 6] >> (cand & 63).astype(np.uint64)) & np.uint64(1)).astype(bool)])[:3000]
+    idx = prefix[rows >> 6] + np.bitwise_count(bits[rows >> 6] & ((np.uint64(1) << (rows & 63).astype(np.uint64))
+                                                                  - np.uint64(1))).astype(np.int64)
+    x = inputs.random_vector(7, b.dim)
+    y_ref = oracle_mod.trunc_sigma_sampled(om, n, eps, V, bits, prefix, rows, x)
+    scale = (2 * np.abs(eps).max() + np.abs(V).sum(axis=1).max()) * n * (om - n)
+    y = b.sigma(eps, V, torch.tensor(x, device="cuda"))[torch.tensor(idx, device="cuda")].cpu().numpy()
+    assert np.abs(y - y_ref).max() <= 1e-13 * scale
+    y32 = b.sigma(eps, V, torch.tensor(x, dtype=torch.float32, device="cuda"))
+    y32 = y32[torch.tensor(idx, device="cuda")].double().cpu().numpy()
+    assert np.abs(y32 - y_ref).max() <= 2e-6 * scale
