@@ -24,11 +24,13 @@
 // start vector, |beta_1 / alpha_1| = ||H q - (q^T H q) q|| / |q^T H q|
 // (Eq. convergence), and stops when it is below tol.
 //
-// Mixed precision: steps k >= 2 of a cycle may run the product in FP32 on an
-// FP32 copy of q_k.  Step 1 (the residual and alpha_1 = q^T H q of the restart
-// vector) is always FP64, so the FP32 error only enters the correction,
-// whose size shrinks with the residual; every stored quantity, dot product
-// and update is FP64.
+// Mixed precision: steps k >= 2 of a cycle run the product in FP32, and the
+// Krylov columns q_2..q_m are stored in FP32 (the next product reads its
+// column directly).  Step 1 (the residual and alpha_1 = q^T H q of the restart
+// vector) is always FP64 and q_1 is stored in FP64, so the FP32 error -- of
+// the products and of the stored columns alike -- only enters the correction
+// sum_{j>=2} y_j q_j, whose size shrinks with the residual; every dot
+// product, norm and update is computed in FP64.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -43,7 +45,7 @@ namespace pd {
 namespace {
 
 struct Layout {
-    size_t coef = 0, scal = 0, partials = 0, Q = 0, p = 0, w = 0, x32 = 0, y32 = 0, total = 0;
+    size_t coef = 0, scal = 0, partials = 0, Q = 0, Q32 = 0, p = 0, w = 0, y32 = 0, total = 0;
     int64_t ld = 0;
     int m = 0;
 };
@@ -66,14 +68,19 @@ Layout layout_for(int64_t dim, int krylov, int precision) {
     L.partials = off;
     off += align256(partial_doubles() * sizeof(double));
     L.Q = off;
-    off += align256((size_t)L.m * L.ld * sizeof(double));
+    if (precision == PD_F32) {
+        // q_1 in FP64, q_2..q_m in FP32
+        off += align256((size_t)L.ld * sizeof(double));
+        L.Q32 = off;
+        off += align256((size_t)std::max(L.m - 1, 1) * L.ld * sizeof(float));
+    } else {
+        off += align256((size_t)L.m * L.ld * sizeof(double));
+    }
     L.p = off;
     off += align256((size_t)L.ld * sizeof(double));
     L.w = off;
     off += align256((size_t)L.ld * sizeof(double));
     if (precision == PD_F32) {
-        L.x32 = off;
-        off += align256((size_t)L.ld * sizeof(float));
         L.y32 = off;
         off += align256((size_t)L.ld * sizeof(float));
     }
@@ -123,7 +130,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
     double *Q = reinterpret_cast<double *>(base + L.Q);
     double *p = reinterpret_cast<double *>(base + L.p);
     double *w = reinterpret_cast<double *>(base + L.w);
-    float *x32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.x32) : nullptr;
+    float *Q32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.Q32) : nullptr;
     float *y32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.y32) : nullptr;
     const int64_t ld = L.ld;
     const int m = L.m;
@@ -144,6 +151,9 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
     if (dscale == 0.0) dscale = 1.0;
 
     PD_HIP(hipMemcpyAsync(coef, &host_coef, sizeof(CoefBlock), hipMemcpyHostToDevice, s));
+    // The vector kernels read FP32 column 2 (with zero weight) while only q_1
+    // exists: it must hold finite values before its first write.
+    if (Q32) PD_HIP(hipMemsetAsync(Q32, 0, (size_t)ld * sizeof(float), s));
     PD_HIP(hipStreamSynchronize(s));
     Dev dev{s, scal, {}};
 
@@ -190,20 +200,20 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
         return fail(PD_EINVAL, "start vector has zero or non-finite norm");
     {
         double sc = 1.0 / std::sqrt(dev.host[kOffNrm]);
-        PD_HIP(launch_scale(w, dim, sc, Q, x32, s));
+        PD_HIP(launch_scale(w, dim, sc, Q, nullptr, s));
     }
 
-    // Fallback for a caller-supplied start: also try the RANDOM start and keep
-    // the vector with the lower Rayleigh quotient (two FP64 products).
+    // Fallback for a caller-supplied start: also try the RANDOM start (in w)
+    // and keep the vector with the lower Rayleigh quotient (two FP64 products).
     if (o->start == PD_START_USER && o->fallback && m >= 2) {
         double rq[2];
         for (int t = 0; t < 2; ++t) {
-            double *q = Q + (size_t)t * ld;
+            double *q = t == 0 ? Q : w;
             if (t == 1) {
                 PD_HIP(launch_fill_random(o->seed, dim, w, s));
                 PD_HIP(launch_norm_sum(w, dim, partials, scal + kOffNrm, scal + kOffSum, s));
                 PD_HIP(dev.fetch(kOffNrm, 1));
-                PD_HIP(launch_scale(w, dim, 1.0 / std::sqrt(dev.host[kOffNrm]), q, nullptr, s));
+                PD_HIP(launch_scale(w, dim, 1.0 / std::sqrt(dev.host[kOffNrm]), w, nullptr, s));
             }
             PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, q, p, s, dsum64, dsum32, tr));
             ++info.iterations;
@@ -213,7 +223,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             rq[t] = dev.host[kOffC];
         }
         if (rq[1] < rq[0]) {
-            PD_HIP(launch_scale(Q + ld, dim, 1.0, Q, x32, s));
+            PD_HIP(launch_scale(w, dim, 1.0, Q, nullptr, s));
             info.fallback_used = 1;
         }
     }
@@ -246,12 +256,13 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
         sc[0] = 1.0;
         for (int k = 0; k < m; ++k) {
             double *qk = Q + (size_t)k * ld;
-            const bool f32_step = x32 && k >= 1;
-            // the product of the stored column k (its FP32 copy for FP32 steps); H q_k = sc[k] * it
+            const bool f32_step = Q32 && k >= 1;
+            // the product of the stored column k (FP32 column for FP32 steps); H q_k = sc[k] * it
             const void *pin = f32_step ? static_cast<const void *>(y32) : static_cast<const void *>(p);
             PD_HIP(hipEventRecord(ev.a, s));
             if (f32_step) {
-                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, x32, y32, s, dsum64, dsum32, tr));
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, Q32 + (size_t)(k - 1) * ld, y32, s, dsum64, dsum32,
+                                    tr));
                 ++info.iterations_f32;
             } else {
                 PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32, tr));
@@ -266,22 +277,23 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             // ps = H q_k - sigma q_k - beta_{k-1} q_{k-1}; c = Q^T ps (alpha_k = sigma + c_k),
             // ||ps||^2 and ||H q_k||^2
             PD_HIP(launch_project(Q, ld, k + 1, dim, pin, f32_step, sp, sc.data(), d.data(), partials,
-                                  scal + kOffC, s));
+                                  scal + kOffC, s, Q32));
             const bool store = k + 1 < m;      // q_{k+1} is needed (else only alpha_k, and beta_0 at k = 0)
             double nrm_v = 0.0;
             if (store || k == 0) {
-                // v = H q_k - Q c, written as the next stored column (or into w), with c' = Q^T v, ||v||^2
-                double *dst = store ? Q + (size_t)(k + 1) * ld : w;
-                float *dst32 = store ? x32 : nullptr;
+                // v = H q_k - Q c, written as the next stored column (FP32 in mixed
+                // precision; or into w), with c' = Q^T v, ||v||^2
+                double *dst = store ? (Q32 ? nullptr : Q + (size_t)(k + 1) * ld) : w;
+                float *dst32 = store && Q32 ? Q32 + (size_t)k * ld : nullptr;
                 PD_HIP(launch_update_project(Q, ld, k + 1, dim, scal + kOffC, sc.data(), d.data(), pin, f32_step,
-                                             sp, dst, dst32, partials, scal + kOffC2, s));
+                                             sp, dst, dst32, partials, scal + kOffC2, s, Q32));
                 PD_HIP(dev.fetch2(kOffC + k, 3, kOffC2 + k + 1, 1));
                 nrm_v = dev.host[kOffC2 + k + 1];
                 const double nrm_ps = dev.host[kOffC + k + 1], nrm_hq = dev.host[kOffC + k + 2];
                 if (!(nrm_v >= kReorthEta * kReorthEta * nrm_ps && nrm_v >= kReorthTau * kReorthTau * nrm_hq)) {
                     // large cancellation: Gram-Schmidt once more, v -= Q c'
                     PD_HIP(launch_update_norm(Q, ld, k + 1, dim, scal + kOffC2, sc.data(), dst, dst32, partials,
-                                              scal + kOffNrm, s));
+                                              scal + kOffNrm, s, Q32));
                     PD_HIP(dev.fetch(kOffNrm, 1));
                     nrm_v = dev.host[kOffNrm];
                     ++info.reorth_second_passes;
@@ -318,11 +330,11 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
         if (tridiag_lowest(m_eff, alpha.data(), beta.data(), &theta, y.data()) != 0)
             return fail(PD_EDEVICE, "tridiagonal eigensolver failed (m=%d)", m_eff);
         for (int j = 0; j < m_eff; ++j) yy[j] = y[j] * sc[j];
-        PD_HIP(launch_combine(Q, ld, m_eff, dim, yy.data(), w, partials, scal + kOffNrm, scal + kOffSum, s));
+        PD_HIP(launch_combine(Q, ld, m_eff, dim, yy.data(), w, partials, scal + kOffNrm, scal + kOffSum, s, Q32));
         PD_HIP(dev.fetch(kOffNrm, 1));
         double nr = std::sqrt(dev.host[kOffNrm]);
         if (!(nr > 0.0)) return fail(PD_EDEVICE, "Ritz vector vanished");
-        PD_HIP(launch_scale(w, dim, 1.0 / nr, Q, x32, s));
+        PD_HIP(launch_scale(w, dim, 1.0 / nr, Q, nullptr, s));
         // Mode 1 (no restart) and the last allowed cycle only measure the Ritz vector next.
         if (o->mode == 1 || cycle >= o->max_restarts) final_check = true;
     }

@@ -129,18 +129,24 @@ size_t partial_doubles();
 // coefficients of stored columns subtracted first: ps = pf - sum_j d_j Qt_j.
 // out_dev[j] = q_j^T ps (j < ncols), out_dev[ncols] = ||ps||^2,
 // out_dev[ncols + 1] = ||pf||^2.
+// Q32 (all of these): null, or the FP32 store of columns j >= 1 (column j at
+// Q32 + (j - 1) ld); column 0 is always FP64 at Q.  With Q32 the first FP32
+// column must hold finite values even when ncols == 1 (it is read with weight 0).
 hipError_t launch_project(const double *Q, int64_t ld, int ncols, int64_t dim, const void *p, bool p_f32, double sp,
                           const double *sc_host, const double *d_host, double *partials, double *out_dev,
-                          hipStream_t s);
-// v = sp p - sum_j (d_j + c_dev[j] sc_j) Qt_j  ->  out (FP64) and out32 (FP32
-// copy, may be null); out_dev[j] = q_j^T v (j < ncols), out_dev[ncols] = ||v||^2.
+                          hipStream_t s, const float *Q32 = nullptr);
+// v = sp p - sum_j (d_j + c_dev[j] sc_j) Qt_j  ->  out (FP64, may be null) and
+// out32 (FP32, may be null); out_dev[j] = q_j^T v (j < ncols), out_dev[ncols] =
+// ||v||^2, both from the FP64 v.
 hipError_t launch_update_project(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
                                  const double *sc_host, const double *d_host, const void *p, bool p_f32, double sp,
-                                 double *out, float *out32, double *partials, double *out_dev, hipStream_t s);
-// v -= sum_j c_dev[j] q_j in place (and out32); nrm2_dev[0] = ||v||^2.
+                                 double *out, float *out32, double *partials, double *out_dev, hipStream_t s,
+                                 const float *Q32 = nullptr);
+// v -= sum_j c_dev[j] q_j in place (and out32); nrm2_dev[0] = ||v||^2.  With v
+// null the vector is FP32 only and is updated in place in out32.
 hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
                               const double *sc_host, double *v, float *out32, double *partials, double *nrm2_dev,
-                              hipStream_t s);
+                              hipStream_t s, const float *Q32 = nullptr);
 // Up to 64 doubles passed to a kernel by value.
 struct SmallVec {
     double v[64];
@@ -152,7 +158,7 @@ hipError_t launch_combine_many(double *Q, int64_t ld, int ncols, int k, int64_t 
 // out = sum_j y[j] Q[j] (j < ncols, y on the host); nrm2_dev[0] = ||out||^2, sum_dev[0] = sum(out).
 hipError_t launch_combine(const double *Q, int64_t ld, int ncols, int64_t dim, const double *y_host,
                           double *out, double *partials, double *nrm2_dev, double *sum_dev,
-                          hipStream_t s);
+                          hipStream_t s, const float *Q32 = nullptr);
 // out = x * scale; optional FP32 copy out32.  out may equal x.
 hipError_t launch_scale(const double *x, int64_t dim, double scale, double *out, float *out32,
                         hipStream_t s);

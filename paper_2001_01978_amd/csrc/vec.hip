@@ -93,13 +93,33 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double *__rest
 // are issued together, and the duplicates get coefficient 0 (their dot
 // products are discarded).
 
+// Krylov column j of row i: column 0 is FP64 (Q); columns j >= 1 are FP64
+// (Q + j ld) or, when Q32 is given (mixed precision), FP32 (Q32 + (j - 1) ld).
+// SPLIT is a template parameter so that every column load is unconditional.
+// Slots j >= ncols repeat column ncols - 1 (weight zero); with ncols == 1 they
+// read the first FP32 column, which the caller keeps finite.
+template <int KMAX, bool SPLIT>
+__device__ __forceinline__ void load_cols(const double *__restrict__ Q, const float *__restrict__ Q32, int64_t ld,
+                                          int ncols, int64_t i, double (&q)[KMAX]) {
+    q[0] = Q[i];
+#pragma unroll
+    for (int j = 1; j < KMAX; ++j) {
+        const int jj = j < ncols ? j : ncols - 1;
+        if constexpr (SPLIT)
+            q[j] = (double)Q32[(size_t)(jj > 0 ? jj - 1 : 0) * ld + i];
+        else
+            q[j] = Q[(size_t)jj * ld + i];
+    }
+}
+
 // With pf = sp * p and ps = pf - sum_j d_j Qt_j (d: the part of the
 // three-term recurrence known in advance), partials: raw_j = sum_i Qt_j[i]
 // ps[i] (j < ncols), sum_i ps[i]^2 (row ncols), sum_i pf[i]^2 (row ncols + 1).
-template <int KMAX, typename TIn>
+template <int KMAX, typename TIn, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void project_kernel(const double *__restrict__ Q, int64_t ld, int ncols,
                                                            int64_t dim, const TIn *__restrict__ p, double sp,
-                                                           SmallVec d, double *__restrict__ partials) {
+                                                           SmallVec d, double *__restrict__ partials,
+                                                           const float *__restrict__ Q32) {
     __shared__ double sh[kWaves * (KMAX + 2)];
     double acc[KMAX], dj[KMAX], nrm[2] = {0.0, 0.0};
 #pragma unroll
@@ -111,8 +131,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const double *__restr
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
         const double pf = sp * (double)p[i];
         double q[KMAX];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
+        load_cols<KMAX, SPLIT>(Q, Q32, ld, ncols, i, q);
         double ps = pf;
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) ps -= q[j] * dj[j];
@@ -126,14 +145,15 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const double *__restr
 
 // v = sp * p - sum_j (d_j + c_j sc_j) Qt_j  ->  out (and out32); partials:
 // raw sum_i Qt_j[i] v[i] (j < ncols) and sum_i v[i]^2 (row ncols).  c: device.
-template <int KMAX, typename TIn>
+template <int KMAX, typename TIn, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void update_project_kernel(const double *__restrict__ Q, int64_t ld,
                                                                   int ncols, int64_t dim,
                                                                   const double *__restrict__ c, SmallVec sc,
                                                                   SmallVec d, const TIn *__restrict__ p,
                                                                   double sp, double *__restrict__ out,
                                                                   float *__restrict__ out32,
-                                                                  double *__restrict__ partials) {
+                                                                  double *__restrict__ partials,
+                                                                  const float *__restrict__ Q32) {
     __shared__ double sh[kWaves * (KMAX + 1)];
     double cj[KMAX], acc[KMAX], nrm[1] = {0.0};
 #pragma unroll
@@ -144,12 +164,11 @@ __global__ __launch_bounds__(kThreads) void update_project_kernel(const double *
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
         double q[KMAX];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
+        load_cols<KMAX, SPLIT>(Q, Q32, ld, ncols, i, q);
         double v = sp * (double)p[i];
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) v -= q[j] * cj[j];
-        out[i] = v;
+        if (out) out[i] = v;
         if (out32) out32[i] = (float)v;
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) acc[j] += q[j] * v;
@@ -159,12 +178,13 @@ __global__ __launch_bounds__(kThreads) void update_project_kernel(const double *
 }
 
 // v -= sum_j (c_j sc_j) Qt_j in place (and out32); partials: sum_i v[i]^2.
-template <int KMAX>
+template <int KMAX, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void update_norm_kernel(const double *__restrict__ Q, int64_t ld,
                                                                int ncols, int64_t dim,
                                                                const double *__restrict__ c, SmallVec sc,
-                                                               double *v_io, float *__restrict__ out32,
-                                                               double *__restrict__ partials) {
+                                                               double *v_io, float *out32,
+                                                               double *__restrict__ partials,
+                                                               const float *__restrict__ Q32) {
     __shared__ double sh[kWaves * 1];
     double cj[KMAX];
 #pragma unroll
@@ -173,22 +193,23 @@ __global__ __launch_bounds__(kThreads) void update_norm_kernel(const double *__r
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
         double q[KMAX];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
-        double v = v_io[i];
+        load_cols<KMAX, SPLIT>(Q, Q32, ld, ncols, i, q);
+        // v_io null: the vector is FP32 only and is updated in place in out32
+        double v = v_io ? v_io[i] : (double)out32[i];
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) v -= q[j] * cj[j];
-        v_io[i] = v;
+        if (v_io) v_io[i] = v;
         if (out32) out32[i] = (float)v;
         acc[0] += v * v;
     }
     block_partials<1>(acc, 1, sh, partials);
 }
 
-template <int KMAX>
+template <int KMAX, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void combine_kernel(const double *__restrict__ Q, int64_t ld, int ncols,
                                                            int64_t dim, SmallVec y, double *__restrict__ out,
-                                                           double *__restrict__ partials) {
+                                                           double *__restrict__ partials,
+                                                           const float *__restrict__ Q32) {
     __shared__ double sh[kWaves * 2];
     double yj[KMAX];
 #pragma unroll
@@ -197,8 +218,7 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const double *__restr
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < dim; i += stride) {
         double q[KMAX];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) q[j] = Q[(size_t)(j < ncols ? j : ncols - 1) * ld + i];
+        load_cols<KMAX, SPLIT>(Q, Q32, ld, ncols, i, q);
         double v = 0.0;
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) v += q[j] * yj[j];
@@ -373,6 +393,20 @@ hipError_t finalize(const double *partials, unsigned nb, int ncols, double scale
         else hipLaunchKernelGGL((KERNEL<64, T>), __VA_ARGS__);                                   \
     } while (0)
 
+// Kernels templated on the column bound and a flag (FP32 columns j >= 1).
+#define PD_DISPATCH_COLS_B(ncols, B, KERNEL, ...)                                                 \
+    do {                                                                                         \
+        if ((ncols) <= 4) hipLaunchKernelGGL((KERNEL<4, B>), __VA_ARGS__);                       \
+        else if ((ncols) <= 8) hipLaunchKernelGGL((KERNEL<8, B>), __VA_ARGS__);                  \
+        else if ((ncols) <= 12) hipLaunchKernelGGL((KERNEL<12, B>), __VA_ARGS__);                \
+        else if ((ncols) <= 16) hipLaunchKernelGGL((KERNEL<16, B>), __VA_ARGS__);                \
+        else if ((ncols) <= 24) hipLaunchKernelGGL((KERNEL<24, B>), __VA_ARGS__);                \
+        else if ((ncols) <= 32) hipLaunchKernelGGL((KERNEL<32, B>), __VA_ARGS__);                \
+        else if ((ncols) <= 48) hipLaunchKernelGGL((KERNEL<48, B>), __VA_ARGS__);                \
+        else hipLaunchKernelGGL((KERNEL<64, B>), __VA_ARGS__);                                   \
+    } while (0)
+#define PD_COMMA ,
+
 hipError_t finalize_scaled(const double *partials, unsigned nb, int nout, const ScaleVec &sc, double *out,
                            hipStream_t s) {
     hipLaunchKernelGGL(finalize_scaled_kernel, dim3(nout), dim3(kThreads), 0, s, partials, (int)nb, sc, out);
@@ -386,17 +420,23 @@ size_t partial_doubles() { return (size_t)kGrid * (kMaxCols + 2); }
 
 hipError_t launch_project(const double *Q, int64_t ld, int ncols, int64_t dim, const void *p, bool p_f32, double sp,
                           const double *sc_host, const double *d_host, double *partials, double *out_dev,
-                          hipStream_t s) {
+                          hipStream_t s, const float *Q32) {
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     unsigned nb = grid_for(dim);
     SmallVec d;
     for (int j = 0; j < 64; ++j) d.v[j] = j < ncols ? d_host[j] : 0.0;
-    if (p_f32)
-        PD_DISPATCH_COLS_T(ncols, float, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
-                           static_cast<const float *>(p), sp, d, partials);
+    if (p_f32 && Q32)
+        PD_DISPATCH_COLS_T(ncols, float PD_COMMA true, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols,
+                           dim, static_cast<const float *>(p), sp, d, partials, Q32);
+    else if (p_f32)
+        PD_DISPATCH_COLS_T(ncols, float PD_COMMA false, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols,
+                           dim, static_cast<const float *>(p), sp, d, partials, Q32);
+    else if (Q32)
+        PD_DISPATCH_COLS_T(ncols, double PD_COMMA true, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols,
+                           dim, static_cast<const double *>(p), sp, d, partials, Q32);
     else
-        PD_DISPATCH_COLS_T(ncols, double, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
-                           static_cast<const double *>(p), sp, d, partials);
+        PD_DISPATCH_COLS_T(ncols, double PD_COMMA false, project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld,
+                           ncols, dim, static_cast<const double *>(p), sp, d, partials, Q32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ScaleVec f;
@@ -406,7 +446,8 @@ hipError_t launch_project(const double *Q, int64_t ld, int ncols, int64_t dim, c
 
 hipError_t launch_update_project(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
                                  const double *sc_host, const double *d_host, const void *p, bool p_f32, double sp,
-                                 double *out, float *out32, double *partials, double *out_dev, hipStream_t s) {
+                                 double *out, float *out32, double *partials, double *out_dev, hipStream_t s,
+                                 const float *Q32) {
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     unsigned nb = grid_for(dim);
     SmallVec sc, d;
@@ -414,12 +455,19 @@ hipError_t launch_update_project(const double *Q, int64_t ld, int ncols, int64_t
         sc.v[j] = j < ncols ? sc_host[j] : 0.0;
         d.v[j] = j < ncols ? d_host[j] : 0.0;
     }
-    if (p_f32)
-        PD_DISPATCH_COLS_T(ncols, float, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
-                           c_dev, sc, d, static_cast<const float *>(p), sp, out, out32, partials);
+    if (p_f32 && Q32)
+        PD_DISPATCH_COLS_T(ncols, float PD_COMMA true, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld,
+                           ncols, dim, c_dev, sc, d, static_cast<const float *>(p), sp, out, out32, partials, Q32);
+    else if (p_f32)
+        PD_DISPATCH_COLS_T(ncols, float PD_COMMA false, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld,
+                           ncols, dim, c_dev, sc, d, static_cast<const float *>(p), sp, out, out32, partials, Q32);
+    else if (Q32)
+        PD_DISPATCH_COLS_T(ncols, double PD_COMMA true, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld,
+                           ncols, dim, c_dev, sc, d, static_cast<const double *>(p), sp, out, out32, partials, Q32);
     else
-        PD_DISPATCH_COLS_T(ncols, double, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols,
-                           dim, c_dev, sc, d, static_cast<const double *>(p), sp, out, out32, partials);
+        PD_DISPATCH_COLS_T(ncols, double PD_COMMA false, update_project_kernel, dim3(nb), dim3(kThreads), 0, s, Q,
+                           ld, ncols, dim, c_dev, sc, d, static_cast<const double *>(p), sp, out, out32, partials,
+                           Q32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ScaleVec f;
@@ -429,13 +477,18 @@ hipError_t launch_update_project(const double *Q, int64_t ld, int ncols, int64_t
 
 hipError_t launch_update_norm(const double *Q, int64_t ld, int ncols, int64_t dim, const double *c_dev,
                               const double *sc_host, double *v, float *out32, double *partials, double *nrm2_dev,
-                              hipStream_t s) {
+                              hipStream_t s, const float *Q32) {
+    if (!v && !out32) return hipErrorInvalidValue;
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     unsigned nb = grid_for(dim);
     SmallVec sc;
     for (int j = 0; j < 64; ++j) sc.v[j] = j < ncols ? sc_host[j] : 0.0;
-    PD_DISPATCH_COLS(ncols, update_norm_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, c_dev, sc, v,
-                     out32, partials);
+    if (Q32)
+        PD_DISPATCH_COLS_B(ncols, true, update_norm_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, c_dev,
+                           sc, v, out32, partials, Q32);
+    else
+        PD_DISPATCH_COLS_B(ncols, false, update_norm_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim,
+                           c_dev, sc, v, out32, partials, Q32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize(partials, nb, 1, 1.0, nrm2_dev, s);
@@ -452,12 +505,17 @@ hipError_t launch_combine_many(double *Q, int64_t ld, int ncols, int k, int64_t 
 }
 
 hipError_t launch_combine(const double *Q, int64_t ld, int ncols, int64_t dim, const double *y_host, double *out,
-                          double *partials, double *nrm2_dev, double *sum_dev, hipStream_t s) {
+                          double *partials, double *nrm2_dev, double *sum_dev, hipStream_t s, const float *Q32) {
     if (ncols < 1 || ncols > kMaxCols) return hipErrorInvalidValue;
     SmallVec y;
     for (int j = 0; j < kMaxCols; ++j) y.v[j] = j < ncols ? y_host[j] : 0.0;
     unsigned nb = grid_for(dim);
-    PD_DISPATCH_COLS(ncols, combine_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, y, out, partials);
+    if (Q32)
+        PD_DISPATCH_COLS_B(ncols, true, combine_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, y, out,
+                           partials, Q32);
+    else
+        PD_DISPATCH_COLS_B(ncols, false, combine_kernel, dim3(nb), dim3(kThreads), 0, s, Q, ld, ncols, dim, y, out,
+                           partials, Q32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = finalize(partials, nb, 1, 1.0, nrm2_dev, s);
