@@ -220,7 +220,8 @@ def main():
 
     common = dict(krylov=args.krylov, tol=args.tol, start="random", seed=1, want_psi=False, verbose=args.verbose)
     nb_mixed = pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f32")
-    ws = pairdiag.device_buffer(nb_mixed)
+    nb_f64 = 0 if args.no_plain else pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f64")
+    ws = pairdiag.device_buffer(max(nb_mixed, nb_f64))
 
     def solve(precision, want_psi=False):
         kw = dict(common, want_psi=want_psi)
