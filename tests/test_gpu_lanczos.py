@@ -212,3 +212,30 @@ def test_argument_errors(pdg):
                              need // 2, None, ctypes.byref(e0), None, None, None, None)
     assert st == pdg.PD_ENOMEM
     del small
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_workspace_filled_with_nan_bytes(pdg, oracle_mod, precision):
+    # Every byte of the caller's workspace starts as 0xFF (NaN in FP32 and
+    # FP64): nothing the solver reads before writing may leak into the result.
+    import torch
+    from paper_2001_01978_amd import inputs
+    om, n = 14, 7
+    _, _, eps, V = inputs.c5_instance(om, n, seed=21)
+    b = pdg.Basis(om, n, store_states=False)
+    import ctypes
+    nb = pdg.workspace_bytes(b, krylov=12, precision=precision)
+    o = pdg.make_opts(krylov=12)
+    nb = max(nb, pdg.load().pd_lanczos_eigs_workspace_bytes(b.handle, 3, ctypes.byref(o)))
+    buf, off = pdg.device_buffer(nb)
+    buf.fill_(255)
+    r = pdg.lanczos_ground(b, eps, V, krylov=12, tol=1e-10, start="random", precision=precision,
+                           workspace=(buf, off), want_psi=False)
+    e0 = oracle_mod.dense_ground(om, n, eps, V)[0]
+    assert r.converged and abs(r.E0 - e0) <= 1e-9 * abs(e0)
+    buf.fill_(255)
+    re = pdg.lanczos_eigs(b, eps, V, 3, krylov=12, tol=1e-10, want_psi=False,
+                          workspace=(buf, off)) if precision == "f64" else None
+    if re is not None:
+        w = oracle_mod.lowest_eigenpairs(om, n, eps, V, 3)[0]
+        np.testing.assert_allclose(re.E, w, rtol=1e-10)
