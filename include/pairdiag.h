@@ -233,8 +233,11 @@ pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V,
  * <= tol; each returned pair is then checked with an explicit FP64 product:
  * E[i] is its Rayleigh quotient and residuals[i] = ||H u - E u|| / |E|.
  * Options: krylov >= nev + 2 (unless krylov >= dim), tol, max_restarts,
- * mode 1 = one cycle, start PD_START_E1 or PD_START_RANDOM (seed),
- * precision PD_F64.  A start vector's Krylov space holds one vector per
+ * mode 1 = one cycle (FP64), start PD_START_E1 or PD_START_RANDOM (seed),
+ * precision PD_F64, or PD_F32: FP32 products on FP32 copies of the columns
+ * until every wanted estimate is below 3e-6 (or, below 1e-4, stops falling), then a fresh
+ * FP64 run from the sum of the wanted Ritz vectors to tol (iterations counts
+ * both, iterations_f32 the first).  A start vector's Krylov space holds one vector per
  * distinct eigenvalue: an exactly degenerate level appears once.
  * Outputs: E (host, nev doubles, ascending); psi_dev (optional, device,
  * nev x dim doubles, state i at psi_dev + i * dim, normalised, sum >= 0);

@@ -16,6 +16,11 @@
 // Jacobi rotations; the restart vectors are formed in place, row by row
 // (launch_combine_many).
 //
+// Mixed precision (PD_F32) runs in two phases: thick restart with FP32
+// products on FP32 copies of the columns until every wanted estimate is below
+// 3e-6 (or, below 1e-4, stops falling), then, since the kept relations carry FP32 errors, a
+// fresh FP64 run started from the sum of the wanted Ritz vectors.
+//
 // A pair counts as converged when its residual estimate
 // |beta_m (y_i)_m| / |theta_i| is below tol; the returned values come from an
 // explicit FP64 product per wanted vector (Rayleigh quotient and residual
@@ -36,7 +41,7 @@ namespace pd {
 namespace {
 
 struct TLayout {
-    size_t coef = 0, scal = 0, partials = 0, Y = 0, Q = 0, p = 0, total = 0;
+    size_t coef = 0, scal = 0, partials = 0, Y = 0, Q = 0, p = 0, x32 = 0, y32 = 0, total = 0;
     int64_t ld = 0;
     int m = 0;
 };
@@ -47,7 +52,7 @@ constexpr double kReorthEta = 0.70710678118654752;
 constexpr double kReorthTau = 1.0 / 128.0;
 constexpr int kMaxM = 64;
 
-TLayout tlayout(int64_t dim, int krylov) {
+TLayout tlayout(int64_t dim, int krylov, int precision) {
     TLayout L;
     L.m = (int)std::min<int64_t>(krylov, dim);
     L.ld = (dim + 63) & ~int64_t(63);
@@ -64,9 +69,20 @@ TLayout tlayout(int64_t dim, int krylov) {
     off += align256((size_t)(L.m + 1) * L.ld * sizeof(double));
     L.p = off;
     off += align256((size_t)L.ld * sizeof(double));
+    if (precision == PD_F32) {
+        L.x32 = off;
+        off += align256((size_t)L.ld * sizeof(float));
+        L.y32 = off;
+        off += align256((size_t)L.ld * sizeof(float));
+    }
     L.total = off;
     return L;
 }
+
+// Mixed precision: the FP32 phase ends when every wanted Ritz residual
+// estimate is below this (well above the FP32 rounding of the products), or
+// when the estimate stops falling.
+constexpr double kSwitchTol = 3e-6;
 
 // Eigenvalues (ascending) and eigenvectors (columns of Z, row-major n x n) of
 // the symmetric matrix A (row-major) by cyclic Jacobi rotations.
@@ -135,7 +151,9 @@ struct Dev {
 
 int thick_keep(int nev, int m) { return std::min(m - 1, std::max(nev, nev + (m - nev) / 2)); }
 
-size_t lanczos_eigs_workspace_bytes(int64_t dim, const pd_lanczos_opts *o) { return tlayout(dim, o->krylov).total; }
+size_t lanczos_eigs_workspace_bytes(int64_t dim, const pd_lanczos_opts *o) {
+    return tlayout(dim, o->krylov, o->precision).total;
+}
 
 pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, const pd_lanczos_opts *o, void *work,
                            size_t work_bytes, double *E_out, double *psi, double *occ_out, double *res_out,
@@ -144,9 +162,8 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
     const int omega = b->omega, n = b->n;
     const int64_t dim = b->dim;
     const TruncSpace *tr = b->truncated ? &b->trunc : nullptr;
-    const TLayout L = tlayout(dim, o->krylov);
+    const TLayout L = tlayout(dim, o->krylov, o->precision);
     if (work_bytes < L.total) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
-    if (o->precision != PD_F64) return fail(PD_EINVAL, "several eigenpairs run in FP64 (precision must be PD_F64)");
     if (nev < 1 || nev > L.m || (L.m < dim && nev > L.m - 2))
         return fail(PD_EINVAL, "nev=%d needs krylov >= nev + 2 (krylov %d, dim %lld)", nev, o->krylov,
                     (long long)dim);
@@ -157,6 +174,9 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
     double *Ydev = reinterpret_cast<double *>(base + L.Y);
     double *Q = reinterpret_cast<double *>(base + L.Q);
     double *p = reinterpret_cast<double *>(base + L.p);
+    const bool mixed = o->precision == PD_F32 && o->mode == 0;
+    float *x32 = mixed ? reinterpret_cast<float *>(base + L.x32) : nullptr;
+    float *y32 = mixed ? reinterpret_cast<float *>(base + L.y32) : nullptr;
     const int64_t ld = L.ld;
     const int m = L.m;
     const int keep = thick_keep(nev, m);
@@ -199,13 +219,38 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
     std::vector<double> theta(m, 0.0), svec(m, 0.0), w, Z;
     int kk = 0;          // kept Ritz vectors at the start of the cycle
     bool converged = false;
-    int cycle = 0;
+    int cycle = 0, cycles_total = 0;
+    // Phase 0 (mixed precision only): FP32 products on FP32 copies of the
+    // columns until the estimates reach kSwitchTol.  The stored relations
+    // H u_i = theta_i u_i + s_i q then carry FP32 errors, so phase 1 starts an
+    // FP64 run afresh from the sum of the wanted Ritz vectors.
+    for (int phase = mixed ? 0 : 1; phase < 2; ++phase) {
+    const bool f32 = phase == 0;
+    const double tol_phase = f32 ? std::max(o->tol, kSwitchTol) : o->tol;
+    double best = INFINITY;
+    int stall = 0;
+    if (phase == 1 && mixed) {
+        std::vector<double> ones(kk, 1.0);
+        PD_HIP(launch_combine(Q, ld, kk, dim, ones.data(), p, partials, scal + kOffNrm, scal + kOffSum, s));
+        PD_HIP(dev.fetch(kOffNrm, 1));
+        PD_HIP(launch_scale(p, dim, 1.0 / std::sqrt(dev.host[kOffNrm]), Q, nullptr, s));
+        kk = 0;
+        std::fill(sc.begin(), sc.end(), 1.0);
+        converged = false;
+    }
+    if (f32) PD_HIP(launch_scale(Q, dim, 1.0, Q, x32, s));
     for (cycle = 0;; ++cycle) {
         int m_eff = m;
         bool breakdown = false;
         for (int j = kk; j < m; ++j) {
             double *qj = Q + (size_t)j * ld;
-            PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qj, p, s, dsum64, dsum32, tr));
+            if (f32) {
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, x32, y32, s, dsum64, dsum32, tr));
+                ++info.iterations_f32;
+            } else {
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qj, p, s, dsum64, dsum32, tr));
+            }
+            const void *pin = f32 ? static_cast<const void *>(y32) : static_cast<const void *>(p);
             ++info.iterations;
             const double sigma = j > kk ? alpha[j - 1] : (kk > 0 ? theta[0] : 0.0);
             std::fill(d.begin(), d.begin() + j + 1, 0.0);
@@ -213,18 +258,18 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
             if (j > kk) d[j - 1] = beta[j - 1] * sc[j - 1];
             if (j == kk)
                 for (int i = 0; i < kk; ++i) d[i] = svec[i] * sc[i];
-            PD_HIP(launch_project(Q, ld, j + 1, dim, p, false, sc[j], sc.data(), d.data(), partials, scal + kOffC,
+            PD_HIP(launch_project(Q, ld, j + 1, dim, pin, f32, sc[j], sc.data(), d.data(), partials, scal + kOffC,
                                   s));
             double *dst = Q + (size_t)(j + 1) * ld;
-            PD_HIP(launch_update_project(Q, ld, j + 1, dim, scal + kOffC, sc.data(), d.data(), p, false, sc[j], dst,
-                                         nullptr, partials, scal + kOffC2, s));
+            PD_HIP(launch_update_project(Q, ld, j + 1, dim, scal + kOffC, sc.data(), d.data(), pin, f32, sc[j], dst,
+                                         f32 ? x32 : nullptr, partials, scal + kOffC2, s));
             PD_HIP(dev.fetch(kOffC, j + 3));
             PD_HIP(dev.fetch(kOffC2 + j + 1, 1));
             double nrm_v = dev.host[kOffC2 + j + 1];
             const double nrm_ps = dev.host[kOffC + j + 1], nrm_hq = dev.host[kOffC + j + 2];
             if (!(nrm_v >= kReorthEta * kReorthEta * nrm_ps && nrm_v >= kReorthTau * kReorthTau * nrm_hq)) {
-                PD_HIP(launch_update_norm(Q, ld, j + 1, dim, scal + kOffC2, sc.data(), dst, nullptr, partials,
-                                          scal + kOffNrm, s));
+                PD_HIP(launch_update_norm(Q, ld, j + 1, dim, scal + kOffC2, sc.data(), dst, f32 ? x32 : nullptr,
+                                          partials, scal + kOffNrm, s));
                 PD_HIP(dev.fetch(kOffNrm, 1));
                 nrm_v = dev.host[kOffNrm];
                 ++info.reorth_second_passes;
@@ -259,11 +304,21 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
             rmax = std::max(rmax, std::fabs(bl * Z[(size_t)(m_eff - 1) * m_eff + i]) /
                                       std::max(std::fabs(w[i]), 1e-3 * dscale));
         info.residual = rmax;
-        converged = want == nev && rmax <= o->tol;
+        converged = want == nev && rmax <= tol_phase;
+        if (f32) {
+            // near the FP32 floor the estimate has stopped falling: FP32 has
+            // done what it can
+            if (rmax < 0.7 * best) {
+                best = rmax;
+                stall = 0;
+            } else if (rmax < 1e-4 && ++stall >= 3) {
+                converged = want == nev;
+            }
+        }
         if (o->verbose)
             std::fprintf(stderr, "[pairdiag] thick cycle %d  E0=%.15g  E%d=%.15g  rho_max=%.3e  products=%d\n", cycle,
                          w[0], want - 1, w[want - 1], rmax, info.iterations);
-        const bool last = converged || breakdown || o->mode == 1 || cycle >= o->max_restarts;
+        const bool last = converged || breakdown || o->mode == 1 || cycles_total + cycle >= o->max_restarts;
         const int newk = last ? want : std::min(keep, m_eff - 1);
         // restart vectors: u_o = sum_j Z[j][o] sc_j Qt_j (o < newk), then q_{m+1} at column newk
         std::vector<double> Yh((size_t)m_eff * newk);
@@ -271,6 +326,8 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
             for (int q = 0; q < newk; ++q) Yh[(size_t)j * newk + q] = Z[(size_t)j * m_eff + q] * sc[j];
         PD_HIP(hipMemcpyAsync(Ydev, Yh.data(), Yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
         PD_HIP(launch_combine_many(Q, ld, m_eff, newk, dim, Ydev, last ? -1 : m_eff, last ? 0.0 : sc[m_eff], s));
+        // the next cycle's first product reads the FP32 copy of column newk
+        if (f32 && !last) PD_HIP(launch_scale(Q + (size_t)newk * ld, dim, 1.0, Q + (size_t)newk * ld, x32, s));
         PD_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < newk; ++i) {
             theta[i] = w[i];
@@ -284,7 +341,10 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
             break;
         }
     }
-    info.restarts = cycle;
+    cycles_total += cycle + 1;
+    if (f32 && !converged) break;   // phase 0 ran out of restarts
+    }
+    info.restarts = cycles_total - 1;
 
     // ---- explicit FP64 check of every wanted vector (columns 0..got-1); fewer
     // than nev only when the start vector's Krylov space is smaller than nev

@@ -430,6 +430,7 @@ class Eigenpairs:
     occ: np.ndarray
     residuals: np.ndarray
     iterations: int
+    iterations_f32: int
     restarts: int
     converged: bool
     seconds: float
@@ -461,7 +462,8 @@ def lanczos_eigs(basis: Basis, eps, V, nev: int, want_psi=True, workspace=None, 
                            _dptr(psi) if psi is not None else None, _hp(occ), _hp(res), ctypes.byref(info),
                            _stream(stream))
     _check(st, allow=(PD_ENOCONV,))
-    return Eigenpairs(E=E, psi=psi, occ=occ, residuals=res, iterations=info.iterations, restarts=info.restarts,
+    return Eigenpairs(E=E, psi=psi, occ=occ, residuals=res, iterations=info.iterations,
+                      iterations_f32=info.iterations_f32, restarts=info.restarts,
                       converged=bool(info.converged), seconds=info.seconds, status=st)
 
 
