@@ -189,9 +189,11 @@ typedef struct {
     int fallback;      /* PD_START_USER only: 1 = also try the RANDOM start and keep the one
                           with the lower Rayleigh quotient (two extra products) */
     int precision;     /* PD_F64 (default) or PD_F32: FP32 products for Krylov steps
-                          k >= 2 of every cycle; the first step of each cycle, all
-                          dot products, the recurrence, the reorthogonalisation, the
-                          tridiagonal solve and the Ritz vectors stay FP64 */
+                          k >= 2 of every cycle, on Krylov vectors q_2..q_m stored in
+                          FP32; the first step of each cycle and q_1, all dot products,
+                          the recurrence, the reorthogonalisation arithmetic, the
+                          tridiagonal solve and the Ritz vectors stay FP64 (the mixed
+                          workspace is about half the FP64 one) */
     int verbose;       /* 1: one line per cycle on stderr */
 } pd_lanczos_opts;
 
