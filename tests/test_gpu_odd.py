@@ -121,3 +121,23 @@ def test_odd_argument_errors(pdg):
     Vb[0, 1] += 1.0
     with pytest.raises(pdg.PairDiagError):
         pdg.lanczos_ground_odd(6, 2, eps, Vb)
+
+
+def test_odd_bench_size_routes_agree(pdg):
+    # The benchmark's odd workload: all 25 blocks of 12 pairs on 24 orbits
+    # (2.7e6 states each).  Beyond the oracle's reach, the two routes are
+    # independent paths (one batched launch with teams vs the single-instance
+    # driver) and must give the same block energies; every E_b lies below the
+    # block's smallest diagonal element.
+    om, n = 25, 12
+    _, _, eps, V = inputs.c5_instance(om, n, seed=0)
+    print("odd bench size", flush=True)
+    a = pdg.lanczos_ground_odd(om, n, eps, V, route="batched", krylov=20, tol=1e-10, start="random", seed=1)
+    s = pdg.lanczos_ground_odd(om, n, eps, V, route="sequential", krylov=20, tol=1e-10, start="random", seed=1)
+    assert a.converged and s.converged
+    np.testing.assert_allclose(a.E_blocks, s.E_blocks, rtol=2e-10)
+    assert a.block == s.block and a.E == pytest.approx(s.E, rel=2e-10)
+    d = 2 * eps + np.diag(V)
+    for b in range(om):
+        lowest_diag = eps[b] + np.sort(np.delete(d, b))[:n].sum()
+        assert a.E_blocks[b] <= lowest_diag
