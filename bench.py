@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-trunc", action="store_true", help="skip the truncated-space leg")
     ap.add_argument("--no-eigs", action="store_true", help="skip the lowest-eigenpairs (thick restart) leg")
     ap.add_argument("--no-scf", action="store_true", help="skip the self-consistent loop leg")
+    ap.add_argument("--no-f64cols", action="store_true",
+                    help="skip the mixed solve with every Krylov column in FP64")
     ap.add_argument("--no-starts", action="store_true", help="skip the E1 and HF start solves (context)")
     ap.add_argument("--no-prev", action="store_true",
                     help="skip the previous-solution start (couplings x1.01 from the converged state)")
@@ -221,7 +223,8 @@ def main():
     common = dict(krylov=args.krylov, tol=args.tol, start="random", seed=1, want_psi=False, verbose=args.verbose)
     nb_mixed = pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f32")
     nb_f64 = 0 if args.no_plain else pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f64")
-    ws = pairdiag.device_buffer(max(nb_mixed, nb_f64))
+    nb_f64c = 0 if args.no_f64cols else pairdiag.workspace_bytes(basis, krylov=args.krylov, precision="f32_f64cols")
+    ws = pairdiag.device_buffer(max(nb_mixed, nb_f64, nb_f64c))
 
     def solve(precision, want_psi=False):
         kw = dict(common, want_psi=want_psi)
@@ -255,6 +258,15 @@ def main():
         r64 = solve("f64")
         plain = r64
         log(f"plain f64: E0={r64.E0:.12f} products={r64.iterations} {r64.seconds:.2f} s")
+
+    # Mixed precision with every Krylov column in FP64 (FP32 copies for the
+    # products), beside the default FP32 storage of q_2..q_m.
+    f64cols = None
+    if not args.no_f64cols:
+        rc = solve("f32_f64cols")
+        f64cols = dict(seconds=rc.seconds, products=rc.iterations, products_f32=rc.iterations_f32,
+                       E0_rel_diff_vs_mixed=abs(rc.E0 - mixed.E0) / abs(mixed.E0))
+        log(f"mixed, FP64 columns: {rc.iterations} products {rc.seconds:.2f} s")
 
     # Previous-solution start: the next problem of a self-consistent sweep,
     # here the same instance with the couplings scaled by 1.01, started from
@@ -474,6 +486,7 @@ def main():
                                  "mixed": mixed.reorth_second_passes,
                                  "warm": warm_r.reorth_second_passes if warm_r else None},
         "warm": warm_info,
+        "mixed_f64_columns": f64cols,
         "previous_solution_start": prev,
         "mixed_other_starts": starts,
         "basis_create_seconds": basis_seconds,

@@ -193,7 +193,9 @@ typedef struct {
                           FP32; the first step of each cycle and q_1, all dot products,
                           the recurrence, the reorthogonalisation arithmetic, the
                           tridiagonal solve and the Ritz vectors stay FP64 (the mixed
-                          workspace is about half the FP64 one) */
+                          workspace is about half the FP64 one); 2: FP32 products as
+                          for PD_F32, every Krylov vector stored in FP64 (the product
+                          reads an FP32 copy of q_k; the FP64 workspace and more) */
     int verbose;       /* 1: one line per cycle on stderr */
 } pd_lanczos_opts;
 

@@ -530,7 +530,7 @@ static pd_status check_opts(const pd_lanczos_opts *o) {
     if (o->max_restarts < 0) return fail(PD_EINVAL, "max_restarts < 0");
     if (o->mode != 0 && o->mode != 1) return fail(PD_EINVAL, "mode must be 0 or 1");
     if (o->start < PD_START_E1 || o->start > PD_START_USER) return fail(PD_EINVAL, "start=%d", o->start);
-    if (o->precision != PD_F64 && o->precision != PD_F32) return fail(PD_EINVAL, "precision=%d", o->precision);
+    if (o->precision < 0 || o->precision > 2) return fail(PD_EINVAL, "precision=%d", o->precision);
     return PD_OK;
 }
 

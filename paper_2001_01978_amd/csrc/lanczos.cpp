@@ -26,7 +26,8 @@
 //
 // Mixed precision: steps k >= 2 of a cycle run the product in FP32, and the
 // Krylov columns q_2..q_m are stored in FP32 (the next product reads its
-// column directly).  Step 1 (the residual and alpha_1 = q^T H q of the restart
+// column directly); precision value 2 keeps every column in FP64 and
+// multiplies an FP32 copy instead.  Step 1 (the residual and alpha_1 = q^T H q of the restart
 // vector) is always FP64 and q_1 is stored in FP64, so the FP32 error -- of
 // the products and of the stored columns alike -- only enters the correction
 // sum_{j>=2} y_j q_j, whose size shrinks with the residual; every dot
@@ -45,7 +46,7 @@ namespace pd {
 namespace {
 
 struct Layout {
-    size_t coef = 0, scal = 0, partials = 0, Q = 0, Q32 = 0, p = 0, w = 0, y32 = 0, total = 0;
+    size_t coef = 0, scal = 0, partials = 0, Q = 0, Q32 = 0, p = 0, w = 0, x32 = 0, y32 = 0, total = 0;
     int64_t ld = 0;
     int m = 0;
 };
@@ -55,6 +56,8 @@ constexpr int kOffC = 0, kOffC2 = 80, kOffNrm = 192, kOffSum = 193, kOffOcc = 25
 // Thresholds of the second Gram-Schmidt pass (see the step description above).
 constexpr double kReorthEta = 0.70710678118654752;   // 1/sqrt(2)
 constexpr double kReorthTau = 1.0 / 128.0;
+// precision value 2: FP32 products, every Krylov column stored in FP64
+constexpr int kMixedF64Cols = 2;
 
 Layout layout_for(int64_t dim, int krylov, int precision) {
     Layout L;
@@ -80,7 +83,12 @@ Layout layout_for(int64_t dim, int krylov, int precision) {
     off += align256((size_t)L.ld * sizeof(double));
     L.w = off;
     off += align256((size_t)L.ld * sizeof(double));
-    if (precision == PD_F32) {
+    if (precision == kMixedF64Cols) {
+        // FP64 columns: the FP32 product reads an FP32 copy of q_k
+        L.x32 = off;
+        off += align256((size_t)L.ld * sizeof(float));
+    }
+    if (precision == PD_F32 || precision == kMixedF64Cols) {
         L.y32 = off;
         off += align256((size_t)L.ld * sizeof(float));
     }
@@ -131,7 +139,8 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
     double *p = reinterpret_cast<double *>(base + L.p);
     double *w = reinterpret_cast<double *>(base + L.w);
     float *Q32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.Q32) : nullptr;
-    float *y32 = o->precision == PD_F32 ? reinterpret_cast<float *>(base + L.y32) : nullptr;
+    float *x32 = o->precision == kMixedF64Cols ? reinterpret_cast<float *>(base + L.x32) : nullptr;
+    float *y32 = o->precision != PD_F64 ? reinterpret_cast<float *>(base + L.y32) : nullptr;
     const int64_t ld = L.ld;
     const int m = L.m;
     const double dsum64 = host_coef.dsum64;
@@ -256,13 +265,13 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
         sc[0] = 1.0;
         for (int k = 0; k < m; ++k) {
             double *qk = Q + (size_t)k * ld;
-            const bool f32_step = Q32 && k >= 1;
+            const bool f32_step = y32 && k >= 1;
             // the product of the stored column k (FP32 column for FP32 steps); H q_k = sc[k] * it
             const void *pin = f32_step ? static_cast<const void *>(y32) : static_cast<const void *>(p);
             PD_HIP(hipEventRecord(ev.a, s));
             if (f32_step) {
-                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, Q32 + (size_t)(k - 1) * ld, y32, s, dsum64, dsum32,
-                                    tr));
+                PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, Q32 ? Q32 + (size_t)(k - 1) * ld : x32, y32, s,
+                                    dsum64, dsum32, tr));
                 ++info.iterations_f32;
             } else {
                 PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32, tr));
@@ -284,7 +293,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
                 // v = H q_k - Q c, written as the next stored column (FP32 in mixed
                 // precision; or into w), with c' = Q^T v, ||v||^2
                 double *dst = store ? (Q32 ? nullptr : Q + (size_t)(k + 1) * ld) : w;
-                float *dst32 = store && Q32 ? Q32 + (size_t)k * ld : nullptr;
+                float *dst32 = store ? (Q32 ? Q32 + (size_t)k * ld : x32) : nullptr;
                 PD_HIP(launch_update_project(Q, ld, k + 1, dim, scal + kOffC, sc.data(), d.data(), pin, f32_step,
                                              sp, dst, dst32, partials, scal + kOffC2, s, Q32));
                 PD_HIP(dev.fetch2(kOffC + k, 3, kOffC2 + k + 1, 1));

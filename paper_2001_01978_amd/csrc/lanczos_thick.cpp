@@ -162,6 +162,8 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
     const int omega = b->omega, n = b->n;
     const int64_t dim = b->dim;
     const TruncSpace *tr = b->truncated ? &b->trunc : nullptr;
+    if (o->precision != PD_F64 && o->precision != PD_F32)
+        return fail(PD_EINVAL, "several eigenpairs take precision PD_F64 or PD_F32");
     const TLayout L = tlayout(dim, o->krylov, o->precision);
     if (work_bytes < L.total) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, L.total);
     if (nev < 1 || nev > L.m || (L.m < dim && nev > L.m - 2))

@@ -378,7 +378,7 @@ def make_opts(krylov=50, tol=1e-10, max_restarts=1000, mode=0, start="e1", seed=
     o.krylov, o.tol, o.max_restarts, o.mode = krylov, tol, max_restarts, mode
     o.start = START[start] if isinstance(start, str) else int(start)
     o.seed = seed
-    o.precision = PD_F32 if precision in ("f32", "mixed", PD_F32) else PD_F64
+    o.precision = {"f32": PD_F32, "mixed": PD_F32, PD_F32: PD_F32, "f32_f64cols": 2, 2: 2}.get(precision, PD_F64)
     o.verbose = int(verbose)
     o.fallback = int(fallback)
     return o

@@ -239,3 +239,22 @@ def test_workspace_filled_with_nan_bytes(pdg, oracle_mod, precision):
     if re is not None:
         w = oracle_mod.lowest_eigenpairs(om, n, eps, V, 3)[0]
         np.testing.assert_allclose(re.E, w, rtol=1e-10)
+
+
+def test_mixed_column_storage_modes_agree(pdg, oracle_mod):
+    # precision 1 stores q_2..q_m in FP32, precision 2 keeps every column in
+    # FP64 (FP32 copies for the products): both refine to the FP64 ground state
+    from paper_2001_01978_amd import inputs
+    om, n = 16, 8
+    _, _, eps, V = inputs.c5_instance(om, n, seed=22)
+    b = pdg.Basis(om, n, store_states=False)
+    assert pdg.workspace_bytes(b, krylov=20, precision="f32") < pdg.workspace_bytes(b, krylov=20, precision="f64")
+    assert pdg.workspace_bytes(b, krylov=20, precision="f32_f64cols") > pdg.workspace_bytes(b, krylov=20,
+                                                                                            precision="f64")
+    ref = oracle_mod.lanczos_ground(om, n, eps, V, krylov=30, tol=1e-11,
+                                    start=inputs.random_vector(5, math.comb(om, n)))
+    for prec in ("f32", "f32_f64cols"):
+        r = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=3, precision=prec)
+        assert r.converged and r.iterations_f32 > 0, prec
+        assert abs(r.E0 - ref["E0"]) <= 1e-9 * abs(ref["E0"]), prec
+        np.testing.assert_allclose(r.occ, ref["occ"], atol=1e-7)
