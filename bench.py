@@ -165,8 +165,8 @@ def stream_probe(torch, gib=8, reps=5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the multi-GPU path is not part of this build "
-              "(see the sharding plan in DESIGN.md); use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the product "
+              "would shard by row ranges with an all-gather of x per step); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
