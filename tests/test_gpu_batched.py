@@ -137,3 +137,36 @@ def test_batched_noconvergence_and_errors(pdg):
         pdg.lanczos_ground_batched([(40, 3, np.zeros(40), -np.ones((40, 40)))])
     with pytest.raises(pdg.PairDiagError):
         pdg.lanczos_ground_batched(insts, krylov=40)
+
+
+def test_batched_full_workload_sampled_vs_oracle(pdg, oracle_mod):
+    """The benchmark's batch as it is timed: 4096 instances (seeds 0..4095),
+    krylov 20, tol 1e-10, autotuned block.  Every instance: converged,
+    sum <N_i> = 2n, 0 <= <N_i> <= 2, E0 below its smallest diagonal element
+    (variational bound).  The smallest instances against the oracle's dense
+    diagonalisation, three mid-size ones against the oracle's Lanczos."""
+    count = 4096
+    insts = [inputs.family3_instance(s) for s in range(count)]
+    print("batched full workload: 4096 instances", flush=True)
+    r = pdg.lanczos_ground_batched(insts, krylov=20, tol=1e-10)
+    assert r.status == pdg.PD_OK and r.converged.all()
+    for q, (om, n, eps, V) in enumerate(insts):
+        occ = r.occ[q]
+        assert abs(occ.sum() - 2 * n) <= 1e-8, q
+        assert occ.min() >= -1e-12 and occ.max() <= 2 + 1e-12, q
+        assert r.E0[q] <= oracle_mod.monopole_min(om, n, eps, V) + 1e-9, q
+    dims = np.array([math.comb(i[0], i[1]) for i in insts])
+    order = np.argsort(dims, kind="stable")
+    for q in list(order[:10]) + list(order[np.searchsorted(dims[order], 1000):][:4]):
+        om, n, eps, V = insts[q]
+        e0, _, occ0, _ = oracle_mod.dense_ground(om, n, eps, V)
+        assert abs(r.E0[q] - e0) <= 1e-10 * abs(e0), (q, om, n)
+        np.testing.assert_allclose(r.occ[q], occ0, atol=1e-8)
+    mid = [q for q in order if 8000 <= dims[q] <= 13000][:3]
+    assert len(mid) == 3
+    for q in mid:
+        om, n, eps, V = insts[q]
+        ref = oracle_mod.lanczos_ground(om, n, eps, V, krylov=30, tol=1e-11,
+                                        start=inputs.random_vector(7, int(dims[q])))
+        assert abs(r.E0[q] - ref["E0"]) <= 1e-10 * abs(ref["E0"]), (q, om, n)
+        np.testing.assert_allclose(r.occ[q], ref["occ"], atol=1e-8)
