@@ -258,3 +258,43 @@ def test_mixed_column_storage_modes_agree(pdg, oracle_mod):
         assert r.converged and r.iterations_f32 > 0, prec
         assert abs(r.E0 - ref["E0"]) <= 1e-9 * abs(ref["E0"]), prec
         np.testing.assert_allclose(r.occ, ref["occ"], atol=1e-7)
+
+
+def test_full_size_mixed_ground_state_sampled(pdg, oracle_mod):
+    """The benchmark's solve as it is timed: Omega=32, n=16 (6.0e8 states),
+    seed-0 instance, random start (seed 1), krylov 20, tol 1e-10, mixed
+    precision.  The eigen-equation on sampled rows with the oracle's own hop
+    enumeration, |(H psi)_r - E0 psi_r| <= rho |E0|; the Perron-Frobenius sign
+    (every V_ij < 0, so only the ground state has no negative component);
+    sum <N_i> = 2n; E0 below the smallest diagonal element; the plain FP64
+    solve of the same problem within 1e-9 relative."""
+    import torch
+    om, n = 32, 16
+    _, _, eps, V = inputs.c5_instance(om, n, seed=0)
+    assert (V < 0).all()
+    b = pdg.Basis(om, n, store_states=False)
+    print("full-size mixed solve omega=32 n=16", flush=True)
+    r = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=1, precision="f32")
+    assert r.converged and r.residual <= 1e-10 and r.iterations_f32 > 0
+    psi = r.psi
+    # components below -1e-6 max|psi| (far beyond the eigenvector error rho |E0| / gap)
+    assert int((psi < -1e-6 * float(psi.abs().max())).sum()) == 0
+    assert abs(float(psi.norm()) - 1.0) <= 1e-12
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([rng.integers(0, b.dim, 3000), np.arange(0, 100),
+                                     np.arange(b.dim - 100, b.dim)]))
+    diag, tg, cf = oracle_mod.row_terms(om, n, eps, V, rows)
+    pr = psi[torch.tensor(rows, device=psi.device)].cpu().numpy()
+    pt = psi[torch.tensor(tg.reshape(-1), device=psi.device)].cpu().numpy().reshape(tg.shape)
+    hpsi = diag * pr + (cf * pt).sum(axis=1)
+    assert np.all(np.abs(hpsi - r.E0 * pr) <= r.residual * abs(r.E0) + 1e-13)
+    assert abs(r.occ.sum() - 2 * n) <= 1e-8 and r.occ.min() >= 0.0 and r.occ.max() <= 2.0
+    assert r.E0 <= oracle_mod.monopole_min(om, n, eps, V)
+    r.psi = None
+    del psi
+    torch.cuda.empty_cache()
+    print("full-size FP64 solve omega=32 n=16", flush=True)
+    f = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=1, precision="f64",
+                           want_psi=False)
+    assert f.converged and abs(r.E0 - f.E0) <= 1e-9 * abs(f.E0)
+    np.testing.assert_allclose(r.occ, f.occ, atol=1e-7)
