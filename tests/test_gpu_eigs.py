@@ -113,3 +113,38 @@ def test_eigs_mixed_precision(pdg, oracle_mod, om, n, nev):
     r = pdg.lanczos_eigs(b, eps, V, nev, krylov=24, tol=1e-10, seed=3, precision="f32")
     assert r.iterations_f32 > 0 and r.iterations > r.iterations_f32
     _check(r, *oracle_mod.lowest_eigenpairs(om, n, eps, V, nev), rtol=1e-10, vtol=1e-6, otol=1e-7)
+
+
+def test_eigs_full_size_sampled(pdg, oracle_mod):
+    """The benchmark's four lowest states as they are timed: Omega=32, n=16
+    (6.0e8 states), seed-0 instance, krylov 20, tol 1e-10, FP64.  For each
+    pair the eigen-equation on sampled rows with the oracle's own hop
+    enumeration, |(H psi)_r - E psi_r| <= res |E|; orthonormal vectors; the
+    ground state alone without a negative component (Perron-Frobenius), the
+    others with both signs."""
+    import torch
+    om, n, nev = 32, 16, 4
+    _, _, eps, V = inputs.c5_instance(om, n, seed=0)
+    b = pdg.Basis(om, n, store_states=False)
+    print("full-size eigenpairs omega=32 n=16 nev=4", flush=True)
+    r = pdg.lanczos_eigs(b, eps, V, nev, krylov=20, tol=1e-10, seed=1)
+    assert r.converged and (r.residuals <= 1e-10).all()
+    assert np.all(np.diff(r.E) > 0)
+    psi = r.psi
+    G = (psi @ psi.T).cpu().numpy()
+    np.testing.assert_allclose(G, np.eye(nev), atol=1e-10)
+    big = [float(psi[i].abs().max()) for i in range(nev)]
+    assert int((psi[0] < -1e-6 * big[0]).sum()) == 0
+    for i in range(1, nev):
+        assert int((psi[i] < -1e-6 * big[i]).sum()) > 0 and int((psi[i] > 1e-6 * big[i]).sum()) > 0
+    rng = np.random.default_rng(12)
+    rows = np.unique(np.concatenate([rng.integers(0, b.dim, 2000), np.arange(0, 50), np.arange(b.dim - 50, b.dim)]))
+    diag, tg, cf = oracle_mod.row_terms(om, n, eps, V, rows)
+    ri = torch.tensor(rows, device=psi.device)
+    ti = torch.tensor(tg.reshape(-1), device=psi.device)
+    for i in range(nev):
+        pr = psi[i][ri].cpu().numpy()
+        pt = psi[i][ti].cpu().numpy().reshape(tg.shape)
+        hpsi = diag * pr + (cf * pt).sum(axis=1)
+        assert np.all(np.abs(hpsi - r.E[i] * pr) <= r.residuals[i] * abs(r.E[i]) + 1e-13), i
+    np.testing.assert_allclose(r.occ.sum(axis=1), 2 * n, atol=1e-8)
