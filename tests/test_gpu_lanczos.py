@@ -266,7 +266,8 @@ def test_full_size_mixed_ground_state_sampled(pdg, oracle_mod):
     precision.  The eigen-equation on sampled rows with the oracle's own hop
     enumeration, |(H psi)_r - E0 psi_r| <= rho |E0|; the Perron-Frobenius sign
     (every V_ij < 0, so only the ground state has no negative component);
-    sum <N_i> = 2n; E0 below the smallest diagonal element; the plain FP64
+    sum <N_i> = 2n; E0 below the smallest diagonal element; the trained
+    network's start reaching the same E0 in fewer products; the plain FP64
     solve of the same problem within 1e-9 relative."""
     import torch
     om, n = 32, 16
@@ -293,6 +294,16 @@ def test_full_size_mixed_ground_state_sampled(pdg, oracle_mod):
     r.psi = None
     del psi
     torch.cuda.empty_cache()
+    # the trained Omega=32 network's start (with the random start as fallback)
+    from paper_2001_01978_amd import warm
+    here = os.path.dirname(os.path.abspath(warm.__file__))
+    net = warm.WarmNet.load(os.path.join(here, "weights", f"warm_o{om}_n{n}.npz"))
+    x0 = b.warm_start(torch.tensor(net.logits(om, eps, V), dtype=torch.float32))
+    print("full-size warm-start solve omega=32 n=16", flush=True)
+    w = pdg.lanczos_ground(b, eps, V, x0=x0, fallback=True, krylov=20, tol=1e-10, precision="f32", want_psi=False)
+    del x0
+    assert w.converged and abs(w.E0 - r.E0) <= 1e-9 * abs(r.E0)
+    assert w.iterations < r.iterations, (w.iterations, r.iterations)
     print("full-size FP64 solve omega=32 n=16", flush=True)
     f = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=1, precision="f64",
                            want_psi=False)
