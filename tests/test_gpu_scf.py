@@ -76,3 +76,34 @@ def test_scf_no_field_is_one_solve_and_errors(pdg):
         pdg.scf_ground(b, eps0, np.full((om, om), np.nan), V)
     m = pdg.scf_ground(b, eps0, _field(om, 9), V, max_iter=2, tol=0.0, krylov=20, start="random")
     assert m.status == pdg.PD_ENOCONV and m.info["iterations"] == 2 and not m.info["converged"]
+
+
+def test_scf_benchmark_size(pdg, oracle_mod):
+    """The benchmark's loop: Omega=24, n=12 (2.7e6 states), seed-0 instance,
+    W = 0.3 (U + U^T)/2 (stream 5), mixing 0.6, field tol 1e-8, solves to
+    1e-11.  Both starts reach the same fixed point; the returned field is that
+    of the returned occupations; the final ground state satisfies the
+    eigen-equation of the final field on sampled rows (the oracle's hop
+    enumeration)."""
+    import torch
+    om, n = 24, 12
+    _, _, eps0, V = inputs.c5_instance(om, n, seed=0)
+    W = _field(om, 5, 0.3)
+    b = pdg.Basis(om, n, store_states=False)
+    kw = dict(mixing=0.6, tol=1e-8, krylov=20, start="random", lanczos_tol=1e-11)
+    a = pdg.scf_ground(b, eps0, W, V, reuse_psi=True, want_psi=True, **kw)
+    c = pdg.scf_ground(b, eps0, W, V, reuse_psi=False, **kw)
+    assert a.info["converged"] and c.info["converged"] and a.info["lanczos_converged"]
+    assert a.info["products"] < c.info["products"]
+    np.testing.assert_allclose(eps0 + W @ a.occ / 2, a.eps, atol=1e-8)
+    np.testing.assert_allclose(a.eps, c.eps, atol=1e-7)
+    np.testing.assert_allclose(a.occ, c.occ, atol=1e-7)
+    assert abs(a.E0 - c.E0) <= 1e-9 * abs(c.E0)
+    assert abs(a.occ.sum() - 2 * n) <= 1e-8
+    psi = a.psi
+    rows = np.unique(np.random.default_rng(13).integers(0, b.dim, 2000))
+    diag, tg, cf = oracle_mod.row_terms(om, n, a.eps, V, rows)
+    pr = psi[torch.tensor(rows, device=psi.device)].cpu().numpy()
+    pt = psi[torch.tensor(tg.reshape(-1), device=psi.device)].cpu().numpy().reshape(tg.shape)
+    hpsi = diag * pr + (cf * pt).sum(axis=1)
+    assert np.all(np.abs(hpsi - a.E0 * pr) <= 1e-11 * abs(a.E0) + 1e-13)
