@@ -87,9 +87,11 @@ pd_status check_sigma_range(pd_basis b) {
     return PD_OK;
 }
 
+}  // namespace
+
 // Device memory check: turns host or foreign pointers, and device ranges that
 // run past the end of their allocation, into PD_EINVAL before any kernel runs.
-pd_status check_device_ptr(const void *p, const char *what, size_t bytes = 0) {
+pd_status check_device_ptr(const void *p, const char *what, size_t bytes) {
     if (!p) return fail(PD_EINVAL, "%s is NULL", what);
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, p);
@@ -114,6 +116,8 @@ pd_status check_device_ptr(const void *p, const char *what, size_t bytes = 0) {
     }
     return PD_OK;
 }
+
+namespace {
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);

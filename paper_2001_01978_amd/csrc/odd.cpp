@@ -144,6 +144,7 @@ pd_status pd_lanczos_ground_odd(int omega, int n, const double *eps, const doubl
     const size_t need = pd_odd_workspace_bytes(omega, n, block, route, o);
     if (need == 0) return fail(PD_EINVAL, "blocks of %d pairs on %d orbits: workspace size query failed", n, om);
     if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+    if ((st = check_device_ptr(work_dev, "work_dev", need)) != PD_OK) return st;
     if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
 
     const double nan = std::numeric_limits<double>::quiet_NaN();

@@ -56,6 +56,9 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 void set_error(const char *fmt, ...);
 pd_status fail(pd_status s, const char *fmt, ...);
 const char *last_error();
+// PD_EINVAL unless p is device (or managed) memory; with bytes != 0, also
+// unless [p, p + bytes) lies inside p's allocation.  No device work.
+pd_status check_device_ptr(const void *p, const char *what, size_t bytes = 0);
 
 #define PD_HIP(call)                                                                    \
     do {                                                                                \

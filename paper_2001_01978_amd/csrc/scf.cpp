@@ -44,10 +44,13 @@ pd_status pd_scf_ground(pd_basis b, const double *eps0, const double *W, const d
     const size_t need = pd_scf_workspace_bytes(b, o);
     if (need == 0) return fail(PD_EINVAL, "bad Lanczos options");
     if (work_bytes < need) return fail(PD_ENOMEM, "workspace %zu bytes, need %zu", work_bytes, need);
+    pd_status st0 = check_device_ptr(work_dev, "work_dev", need);
+    if (st0 != PD_OK) return st0;
     if (reinterpret_cast<uintptr_t>(work_dev) & 255) return fail(PD_EINVAL, "work_dev must be 256-byte aligned");
     if (psi0_dev) {
         const char *a = reinterpret_cast<const char *>(psi0_dev), *w = static_cast<const char *>(work_dev);
         const size_t nb = (size_t)b->dim * sizeof(double);
+        if ((st0 = check_device_ptr(psi0_dev, "psi0_dev", nb)) != PD_OK) return st0;
         if (a < w + work_bytes && w < a + nb) return fail(PD_EINVAL, "psi0_dev overlaps the workspace");
     }
     double *psi = static_cast<double *>(work_dev);

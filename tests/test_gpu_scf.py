@@ -107,3 +107,28 @@ def test_scf_benchmark_size(pdg, oracle_mod):
     pt = psi[torch.tensor(tg.reshape(-1), device=psi.device)].cpu().numpy().reshape(tg.shape)
     hpsi = diag * pr + (cf * pt).sum(axis=1)
     assert np.all(np.abs(hpsi - a.E0 * pr) <= 1e-11 * abs(a.E0) + 1e-13)
+
+
+def test_scf_rejects_host_pointers_before_device_work(pdg):
+    import ctypes
+    om, n = 10, 5
+    _, _, eps0, V = inputs.c5_instance(om, n, seed=4)
+    W = _field(om, 9)
+    b = pdg.Basis(om, n, store_states=False)
+    L = pdg.load()
+    o = pdg.make_opts(krylov=20, start="random")
+    so = pdg.ScfOpts(max_iter=50, tol=1e-8, mixing=0.5, reuse_psi=1)
+    nb = L.pd_scf_workspace_bytes(b.handle, ctypes.byref(o))
+    buf, off = pdg.device_buffer(nb)
+    eps, occ, e0 = np.empty(om), np.empty(om), ctypes.c_double()
+    host = np.zeros(b.dim)
+    args = (b.handle, pdg._hp(eps0), pdg._hp(W), pdg._hp(V), ctypes.byref(so), ctypes.byref(o))
+    st = L.pd_scf_ground(*args, ctypes.c_void_p(buf.data_ptr() + off), nb, pdg._hp(eps), pdg._hp(occ),
+                         ctypes.byref(e0), pdg._hp(host), None, None)
+    assert st == pdg.PD_EINVAL                      # psi0_dev on the host
+    hw = np.zeros(nb // 8 + 1)
+    st = L.pd_scf_ground(*args, pdg._hp(hw), nb, pdg._hp(eps), pdg._hp(occ), ctypes.byref(e0), None, None, None)
+    assert st == pdg.PD_EINVAL                      # workspace on the host
+    st = L.pd_scf_ground(*args, ctypes.c_void_p(buf.data_ptr() + off), nb, pdg._hp(eps), pdg._hp(occ),
+                         ctypes.byref(e0), None, None, None)
+    assert st == pdg.PD_OK
