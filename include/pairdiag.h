@@ -266,7 +266,10 @@ pd_status pd_lanczos_eigs(pd_basis b, const double *eps, const double *V, int ne
  * o->start: E1, HF or RANDOM (the first solve).  work_dev: device, 256-byte
  * aligned, pd_scf_workspace_bytes(b, o) bytes.  Outputs (host): eps_out (the
  * eps of the last solve), occ_out (its <N_i>), *E0 (its ground-state energy);
- * psi0_dev (optional, device, dim doubles) its ground state; info.
+ * psi0_dev (optional, device, dim doubles, outside the workspace) its ground
+ * state; info.  Host or foreign pointers, short allocations, mixing outside
+ * (0, 1], a non-finite W or a PD_START_USER start give PD_EINVAL (a short
+ * work_bytes PD_ENOMEM) before any device work.
  * Returns PD_ENOCONV (outputs filled) if max_iter is reached first.
  * Synchronises `stream`. */
 typedef struct {
