@@ -96,3 +96,56 @@ def test_instance_recipes_shapes_and_signs():
         om, n, eps, V = inputs.family3_instance(seed)
         assert 10 <= om <= 24 and math.ceil(om / 4) <= n <= om // 2
         assert np.array_equal(V, V.T) and np.all(V < 0)
+
+
+@pytest.mark.parametrize("om,n,bins", [(10, 5, 1000), (12, 4, 10**8), (9, 0, 7), (9, 9, 5), (14, 7, 3), (7, 3, 1)])
+def test_trunc_select_without_a_cut_runs_on_the_host(oracle_mod, om, n, bins):
+    """When the space fits the limit, pd_trunc_select needs no device: the
+    extreme diagonals (n lowest / highest pair energies, stable order) and the
+    bin scale against the oracle, bit for bit, and every state kept."""
+    L = pdg.load()
+    _, _, eps, V = inputs.c5_instance(om, n, seed=om + n)
+    full = math.comb(om, n)
+    info = pdg.TruncInfo()
+    st = L.pd_trunc_select(om, n, pdg._hp(eps), pdg._hp(V), full, bins, None, 0, ctypes.byref(info), None)
+    assert st == pdg.PD_OK, L.pd_last_error()
+    ref = oracle_mod.trunc_select(om, n, eps, V, full, bins, method="numpy")
+    assert (info.full_dim, info.kept, info.cut_bin, info.bins, info.limit) == (full, full, bins - 1, bins, full)
+    assert info.dmin == ref["dmin"] and info.dmax == ref["dmax"] and info.scale == ref["scale"]
+    if ref["scale"] > 0:
+        assert info.cutoff == ref["dmin"] + bins / ref["scale"]
+    else:
+        assert info.cutoff == ref["dmin"]
+
+
+def test_new_entry_points_reject_bad_arguments_before_device_work():
+    L = pdg.load()
+    om, n = 10, 4
+    _, _, eps, V = inputs.c5_instance(om, n, seed=3)
+    o = pdg.make_opts(krylov=20, start="random")
+    E, blk = ctypes.c_double(), ctypes.c_int()
+
+    def odd(omega, nn, block, route, opts=o):
+        return L.pd_lanczos_ground_odd(omega, nn, pdg._hp(eps), pdg._hp(V), block, route, ctypes.byref(opts),
+                                       None, 0, ctypes.byref(E), ctypes.byref(blk), None, None, None, None)
+    assert odd(1, 0, 0, 0) == pdg.PD_EINVAL                 # omega < 2
+    assert odd(om, om, 0, 0) == pdg.PD_EINVAL               # n > omega - 1 pairs
+    assert odd(om, n, om + 1, 0) == pdg.PD_EINVAL           # block outside [0, omega]
+    assert odd(om, n, 0, 3) == pdg.PD_EINVAL                # unknown route
+    assert odd(om, n, 2, 2) == pdg.PD_EINVAL                # batched route solves all blocks
+    assert odd(om, n, 0, 0, pdg.make_opts(start="user")) == pdg.PD_EINVAL
+    assert L.pd_odd_workspace_bytes(1, 0, 0, 0, ctypes.byref(o)) == 0
+    assert L.pd_odd_workspace_bytes(om, n, 0, 3, ctypes.byref(o)) == 0
+    big = pdg.make_opts(krylov=40)
+    assert odd(om, n, 0, 2, big) == pdg.PD_ERANGE           # krylov above the batched limit
+    info = pdg.TruncInfo()
+    for args in ((0, 0, 10, 100), (om, om + 1, 10, 100), (om, n, 0, 100), (om, n, 10, 0), (om, n, 10, 2 ** 31)):
+        w, nn, lim, bins = args
+        assert L.pd_trunc_select(w, nn, pdg._hp(eps), pdg._hp(V), lim, bins, None, 0, ctypes.byref(info),
+                                 None) == pdg.PD_EINVAL, args
+    assert L.pd_trunc_select_bytes(om, n, 0) == 0 and L.pd_trunc_select_bytes(70, 3, 10) == 0
+    assert L.pd_lanczos_eigs(None, pdg._hp(eps), pdg._hp(V), 2, ctypes.byref(o), None, 0, None, None, None, None,
+                             None, None) == pdg.PD_EINVAL
+    so = pdg.ScfOpts(max_iter=10, tol=1e-8, mixing=0.5, reuse_psi=1)
+    assert L.pd_scf_ground(None, pdg._hp(eps), pdg._hp(V), pdg._hp(V), ctypes.byref(so), ctypes.byref(o), None, 0,
+                           None, None, ctypes.byref(E), None, None, None) == pdg.PD_EINVAL
