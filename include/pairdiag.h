@@ -154,15 +154,17 @@ pd_status pd_basis_truncation(pd_basis b, int *truncated, int64_t *full_dim);
  * symmetric and finite.  x, y: device vectors of dim elements of dtype dt
  * (PD_F64: double gathers and accumulation; PD_F32: float gathers, float
  * accumulation, coefficients rounded to float).  x and y must not overlap.
- * The coefficients are kept in the handle's device block: when they differ
- * from the previous call on this handle they are uploaded on `stream` and
- * the stream is synchronised; otherwise the call is fully asynchronous.
- * The same block holds the kernel's per-XCD tile counters (zero between
- * launches), so calls on one handle must not overlap in time: issue them on
- * one stream, or synchronise between streams.  For concurrent products,
- * create one handle per stream (without stored states a handle takes
- * pd_basis_bytes(omega, n, 0), about 50 KB).  pd_lanczos_ground keeps its
- * own copy of the block in its workspace and is not restricted this way.
+ * The handle's device buffer holds 4 coefficient blocks, each with the
+ * kernel's per-XCD tile counters.  A call takes a block that is unused, or
+ * was last used on the same stream (stream order protects it), or whose last
+ * product has finished; if every block is busy on other streams, `stream`
+ * first waits for the oldest one's product.  So concurrent calls on one
+ * handle from different streams and host threads are allowed and each
+ * returns the complete product (at most 4 of them run truly in parallel).
+ * When the coefficients differ from those the chosen block holds they are
+ * uploaded on `stream` and the stream is synchronised; otherwise the call is
+ * fully asynchronous.  pd_lanczos_ground keeps its own block in its
+ * workspace.
  */
 pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
                    const void *x_dev, void *y_dev, hipStream_t stream);
@@ -178,6 +180,9 @@ pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
  * ground-state Ritz vector.  Convergence (Eq. convergence): the restarted
  * vector q has rho = ||H q - (q^T H q) q|| / |q^T H q| <= tol; rho is computed
  * with an FP64 product.  mode 1 stops after the first cycle (no restart).
+ * In mixed precision the FP64 refinement (an FP64 product of the restart
+ * vector, which gives alpha_1 and the residual) runs at the start of every
+ * cycle; there is no option to space it out (no refine_every).
  */
 typedef struct {
     int krylov;        /* vectors per cycle (Lanc_Limit); 2..64; default 50 */
@@ -406,7 +411,9 @@ pd_status pd_warm_start(pd_basis b, const float *logits_dev, double *x0_dev, hip
 typedef struct { int in, h1, h2, out; } pd_mlp_shape;
 size_t pd_mlp_param_count(const pd_mlp_shape *s);
 size_t pd_mlp_workspace_bytes(const pd_mlp_shape *s, int batch);
-/* logits_dev: batch x out (device). */
+/* logits_dev: batch x out (device).  On return the workspace begins with
+ * Z1 = X W1 + b1, the first layer's pre-activations (batch x h1 floats,
+ * row-major). */
 pd_status pd_mlp_forward(const pd_mlp_shape *s, const float *params_dev, const float *X_dev, int batch,
                          void *work_dev, size_t work_bytes, float *logits_dev, hipStream_t stream);
 /* Forward, loss and backward: grads_dev (param_count floats) receives d loss / d params,
@@ -417,6 +424,25 @@ pd_status pd_mlp_backward(const pd_mlp_shape *s, const float *params_dev, const 
 /* Adam (Kingma & Ba) with bias correction, step >= 1; m, v: state arrays of count floats. */
 pd_status pd_mlp_adam(int64_t count, float *params_dev, const float *grads_dev, float *m_dev, float *v_dev,
                       int step, float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
+/* ------------------------------------------------------------------ measurement
+ * Achievable HBM bandwidth (not part of the method; the yardstick its
+ * streaming kernels and its product are measured against).  One launch of a
+ * streaming kernel over n floats with 16-byte vector accesses, every element
+ * touched once, so the bytes it moves are exactly pd_stream_probe_bytes:
+ *   PD_PROBE_READ   sums a; one partial sum per workgroup goes to c_dev[0..]   4 n bytes
+ *   PD_PROBE_COPY   c = a                                                      8 n bytes
+ *   PD_PROBE_TRIAD  c = a + 0.5 b                                             12 n bytes
+ *   PD_PROBE_WRITE  c = 0.5                                                    4 n bytes
+ * OR-ing PD_PROBE_NONTEMPORAL marks the accesses as streaming (no reuse).
+ * a_dev, b_dev, c_dev: device float arrays of n elements (a unused by WRITE,
+ * b used by TRIAD only; pass NULL for unused ones); c must not overlap a or b.
+ * n: a positive multiple of 1024.  Asynchronous on `stream`.  PD_EINVAL on
+ * a bad kind, n, pointer or overlap (no device work). */
+enum { PD_PROBE_READ = 0, PD_PROBE_COPY = 1, PD_PROBE_TRIAD = 2, PD_PROBE_WRITE = 3, PD_PROBE_NONTEMPORAL = 16 };
+int64_t pd_stream_probe_bytes(int kind, int64_t n);
+pd_status pd_stream_probe(int kind, const float *a_dev, const float *b_dev, float *c_dev, int64_t n,
+                          hipStream_t stream);
 
 /* ------------------------------------------------------------------ host utility
  * Lowest eigenpair of the m x m symmetric tridiagonal matrix with diagonal

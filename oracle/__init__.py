@@ -6,7 +6,8 @@ library (the C part lives in pd_oracle.c and is built with gcc by build()).
 Everything is FP64.
 
 Functions and the passages they follow:
-  binom, basis_alg1, hash_index, unhash, index_bsearch   Sec. 3.1-3.2, Eq. extcmn, Alg. conversion, Eq. hash
+  binom, basis_alg1, next_state, hash_index, unhash,    Sec. 3.1-3.2, Eq. extcmn, Tab. data (ascending basis, the
+    index_bsearch                                         order of Alg. conversion), Eq. hash, binary search
   sigma, sigma_sampled, row_terms, dense_h                Sec. 3.3, Eq. hamiltonian2, Eq. diagonal
   dense_ground                                            E0 as the lowest eigenvalue of the explicit H
   lanczos_ground                                          Sec. 3.4, Alg. lanczos, full reorthogonalisation,
@@ -18,8 +19,9 @@ Functions and the passages they follow:
   scf_ground                                              Sec. 1 and 6: the exact solution inside a self-consistent
                                                           loop (synthetic mean field eps0 + W <N>/2, linear mixing)
   diagonals, trunc_select, sigma(index_mode=              Sec. 3.5 truncation (diagonal histogram, cut, binary
-    'bsearch_truncated'), trunc_bits,                     search in the truncated basis; C histogram, kept bits and
-    trunc_sigma_sampled                                   sampled rows for spaces too large to store)
+    'bsearch_truncated'), trunc_kept_ranks,               search in the truncated basis; for spaces too large to
+    trunc_sigma_sampled                                   store: C histogram, the ascending kept ranks, sampled
+                                                          rows with every index found by binary search in them)
   richardson_evb                                          constant-G check (Richardson equations, eigenvalue form)
   pbcs_vector                                             number-projected product start vector (warm start)
   mlp_*                                                   FP64 reference of the warm-start network
@@ -74,9 +76,10 @@ def lib():
         L.or_dense_h.restype, L.or_dense_h.argtypes = i32, [i32, i32, P, P, P, i64, P]
         L.or_trunc_count.restype = i32
         L.or_trunc_count.argtypes = [i32, i32, P, dbl, dbl, i64, i32, i64, i64, P]
-        L.or_trunc_bits.restype, L.or_trunc_bits.argtypes = i32, [i32, i32, P, dbl, dbl, i64, i64, P]
+        L.or_trunc_kept_ranks.restype = i64
+        L.or_trunc_kept_ranks.argtypes = [i32, i32, P, dbl, dbl, i64, i64, P, i64]
         L.or_trunc_sigma_sampled.restype = i32
-        L.or_trunc_sigma_sampled.argtypes = [i32, i32, P, P, P, P, P, i64, P, P]
+        L.or_trunc_sigma_sampled.argtypes = [i32, i32, P, P, P, i64, P, i64, P, P]
         L.or_sigma_block.restype = i32
         L.or_sigma_block.argtypes = [i32, i32, P, P, i64, P, i64, i64, P]
         L.or_row_terms.restype = dbl
@@ -111,7 +114,8 @@ def next_state(s: int) -> int:
 
 
 def basis_alg1(omega: int, n: int) -> np.ndarray:
-    """All C^n_omega states in generation order by the '01' inversion iteration."""
+    """All C^n_omega states in ascending order (Tab. data; the order Alg.
+    conversion visits them), each the successor of the one before."""
     d = binom(omega, n)
     out = np.empty(d, dtype=np.uint64)
     got = lib().or_basis_alg1(omega, n, _p(out), d)
@@ -173,8 +177,9 @@ def sigma_sampled(omega: int, n: int, eps, V, x, rows) -> np.ndarray:
 
 
 def sigma_block(omega: int, n: int, eps, V, x, r0: int, r1: int) -> np.ndarray:
-    """(H x)[r0:r1] as the paper's program computes it: states by the '01'
-    inversion, targets by the hash (no stored basis; x is the full vector)."""
+    """(H x)[r0:r1] as the paper's program computes it: states one after the
+    other by the basis successor, targets by the hash (no stored basis; x is
+    the full vector)."""
     eps, V = _check_h(omega, eps, V)
     x = _f64(x)
     y = np.empty(r1 - r0)
@@ -435,31 +440,32 @@ def scf_ground(omega: int, n: int, eps0, W, V, mixing: float = 0.5, tol: float =
     return dict(eps=eps, occ=occ, E0=E0, iterations=max_iter, change=change)
 
 
-def trunc_bits(omega: int, n: int, eps, V, sel, bins: int = 10**8):
-    """Kept-state bits of a selection from trunc_select (one uint64 per 64
-    full ranks), recomputed state by state in C, and the exclusive prefix
-    count of kept states per word."""
+def trunc_kept_ranks(omega: int, n: int, eps, V, sel, bins: int = 10**8) -> np.ndarray:
+    """Ascending full-space ranks of the states a selection from trunc_select
+    keeps (bin <= cut), recomputed state by state in C."""
     eps, V = _check_h(omega, eps, V)
     d = np.zeros(62)
     d[:omega] = 2.0 * eps + np.diag(V)
-    W = (sel["full_dim"] + 63) // 64
-    bits = np.zeros(W, dtype=np.uint64)
-    lib().or_trunc_bits(omega, n, _p(d), sel["dmin"], sel["scale"], bins, sel["cut_bin"],
-                        bits.ctypes.data_as(ctypes.c_void_p))
-    cnt = np.bitwise_count(bits).astype(np.int64)
-    prefix = np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.int64)
-    return bits, prefix
+    out = np.empty(int(sel["kept"]), dtype=np.int64)
+    got = lib().or_trunc_kept_ranks(omega, n, _p(d), sel["dmin"], sel["scale"], bins, sel["cut_bin"],
+                                    out.ctypes.data_as(ctypes.c_void_p), out.size)
+    if got != out.size:
+        raise RuntimeError(f"selection keeps {got} states, expected {out.size}")
+    return out
 
 
-def trunc_sigma_sampled(omega: int, n: int, eps, V, bits, prefix, ranks, x) -> np.ndarray:
+def trunc_sigma_sampled(omega: int, n: int, eps, V, kept, ranks, x) -> np.ndarray:
     """Rows of the truncated product (H restricted to the kept states) for the
-    listed kept full ranks, with targets located by the hash and the bits."""
+    listed kept full ranks.  kept: ascending kept full ranks (x is indexed by
+    position in it); each row's position and each target's are found by
+    binary search in kept (Sec. 3.2, Sec. 3.5), targets not kept dropped."""
     eps, V = _check_h(omega, eps, V)
     x = _f64(x)
+    kept = np.ascontiguousarray(kept, dtype=np.int64)
     ranks = np.ascontiguousarray(ranks, dtype=np.int64)
     y = np.empty(ranks.size)
-    rc = lib().or_trunc_sigma_sampled(omega, n, _p(eps), _p(V), bits.ctypes.data_as(ctypes.c_void_p),
-                                      prefix.ctypes.data_as(ctypes.c_void_p), _p(ranks), ranks.size, _p(x), _p(y))
+    rc = lib().or_trunc_sigma_sampled(omega, n, _p(eps), _p(V), kept.ctypes.data_as(ctypes.c_void_p), kept.size,
+                                      _p(ranks), ranks.size, _p(x), _p(y))
     if rc != 0:
         raise RuntimeError("a listed rank is not kept")
     return y

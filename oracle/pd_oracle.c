@@ -8,7 +8,8 @@
  *
  * Everything here follows the paper's definitions as literally as possible:
  *   - binomial numbers C^m_n with the extension C = 0 for n < m   (Sec. 3.1, Eq. extcmn)
- *   - basis by the '01' inversion iteration                        (Sec. 3.1, Alg. conversion)
+ *   - basis in ascending order (Tab. data, the order of Alg. conversion),
+ *     successor = next larger integer with as many set bits       (Sec. 3.1)
  *   - index by binary search over the stored basis                 (Sec. 3.2)
  *   - index by the hash f(|i>) = 1 + sum_j C^j_{O_j - 1}           (Sec. 3.2, Eq. hash)
  *   - diagonal H_ii = sum_n (2 eps_n + V_nn) <i|S+_n S-_n|i>       (Sec. 3.3, Eq. diagonal)
@@ -52,25 +53,27 @@ uint64_t or_binom(int n, int m)
     return cmn[n][m];
 }
 
-/* Alg. conversion ('01' inversion): scan from the lowest bit; each set bit is
- * cleared; if the bit above it is clear, that bit is set and the scan stops;
- * otherwise the cleared bit is collected into the tail (which is refilled from
- * the lowest digit).  The paper prints the loop as i = 0, 2, ..., 61; the text
- * and the worked example need step 1, which is what is done here. */
-uint64_t or_next_state(uint64_t in)
+/* Successor in the basis order.  Sec. 3.1 lists the states of n pairs in
+ * ascending order (Tab. data, the order Alg. conversion visits them), so the
+ * successor of s is the smallest integer above s with the same number of set
+ * bits.  Written from that definition: let the lowest run of ones of s start
+ * at bit p and hold L ones.  Any larger number with the same count must set a
+ * clear bit above p; the smallest such change sets bit p + L (the first clear
+ * bit above the run), clears the run, and puts the L - 1 ones left over on the
+ * lowest bits 0 .. L-2.  Returns ~0 when no successor exists below 2^64. */
+uint64_t or_next_state(uint64_t s)
 {
-    uint64_t tail = 0;
-    for (int i = 0; i <= 61; ++i) {
-        if ((in >> i) & 1ull) {
-            in &= ~(1ull << i);
-            if (!((in >> (i + 1)) & 1ull)) {
-                in |= 1ull << (i + 1);
-                break;
-            }
-            tail = (tail << 1) | 1ull;
-        }
-    }
-    return in + tail;
+    if (s == 0) return ~0ull;
+    int p = 0;
+    while (!((s >> p) & 1ull)) ++p;
+    int L = 0;
+    while (p + L < 64 && ((s >> (p + L)) & 1ull)) ++L;
+    if (p + L >= 64) return ~0ull;
+    uint64_t t = s;
+    for (int i = p; i < p + L; ++i) t &= ~(1ull << i);
+    t |= 1ull << (p + L);
+    for (int i = 0; i < L - 1; ++i) t |= 1ull << i;
+    return t;
 }
 
 /* Sec. 3.1: start at the minimum 0..01..1 (n pairs in the lowest orbits) and
@@ -231,7 +234,7 @@ double or_row_terms(int omega, int n, const double *eps, const double *V, int64_
 }
 
 /* y[r - r0] = (H x)[r] for r in [r0, r1) the way the paper's program runs:
- * states by the '01' inversion from the block start, targets by the hash.
+ * states by the basis successor from the block start, targets by the hash.
  * Each thread takes a contiguous chunk and finds its first state from the
  * inverse hash.  Used for CPU timing. */
 int or_sigma_block(int omega, int n, const double *eps, const double *V, int64_t dim,
@@ -309,8 +312,8 @@ static int64_t diag_bin(uint64_t s, const double *d, double dmin, double scale, 
 
 /* Counts of the keys bin >> shift over the whole (omega, n) space, for keys in
  * [lo, lo + len): out[key - lo] (len <= 65536).  Every 64 ranks start from the
- * inverse hash and continue by '01' inversion; counts are per thread, then
- * added. */
+ * inverse hash and continue by the basis successor; counts are per thread,
+ * then added. */
 int or_trunc_count(int omega, int n, const double *d, double dmin, double scale, int64_t bins, int shift,
                    int64_t lo, int64_t len, uint64_t *out)
 {
@@ -339,40 +342,76 @@ int or_trunc_count(int omega, int n, const double *d, double dmin, double scale,
     return 0;
 }
 
-/* bits[w] bit j = 1 iff the state of rank 64 w + j lies in a bin <= cut. */
-int or_trunc_bits(int omega, int n, const double *d, double dmin, double scale, int64_t bins, int64_t cut,
-                  uint64_t *bits)
+/* Ascending full-space ranks of the kept states (bin <= cut) into out (cap
+ * entries); returns their number, or -1 if cap is too small.  Ranks are
+ * visited in chunks of 65536: a first pass counts the kept states of every
+ * chunk, a running sum gives each chunk its first output position, a second
+ * pass writes them.  States by the inverse hash at a chunk start, then the
+ * basis successor. */
+int64_t or_trunc_kept_ranks(int omega, int n, const double *d, double dmin, double scale, int64_t bins, int64_t cut,
+                            int64_t *out, int64_t cap)
 {
     cmn_init();
-    const int64_t dim = (int64_t)or_binom(omega, n), W = (dim + 63) / 64;
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t w = 0; w < W; ++w) {
-        const int64_t r0 = w * 64;
-        const int cnt = (int)(dim - r0 < 64 ? dim - r0 : 64);
-        uint64_t s = or_unhash(r0, n), m = 0;
-        for (int j = 0; j < cnt; ++j) {
-            if (diag_bin(s, d, dmin, scale, bins) <= cut) m |= 1ull << j;
-            if (j + 1 < cnt) s = or_next_state(s);
+    const int64_t dim = (int64_t)or_binom(omega, n), chunk = 65536, nc = (dim + chunk - 1) / chunk;
+    int64_t *start = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+    if (!start) return -1;
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t c = 0; c < nc; ++c) {
+            const int64_t r0 = c * chunk, r1 = r0 + chunk < dim ? r0 + chunk : dim;
+            int64_t pos = start[c], cnt = 0;
+            uint64_t s = or_unhash(r0, n);
+            for (int64_t r = r0; r < r1; ++r) {
+                if (diag_bin(s, d, dmin, scale, bins) <= cut) {
+                    if (pass == 1) out[pos++] = r;
+                    ++cnt;
+                }
+                if (r + 1 < r1) s = or_next_state(s);
+            }
+            if (pass == 0) start[c + 1] = cnt;
         }
-        bits[w] = m;
+        if (pass == 0) {
+            for (int64_t c = 0; c < nc; ++c) start[c + 1] += start[c];
+            if (start[nc] > cap) {
+                free(start);
+                return -1;
+            }
+        }
     }
-    return 0;
+    const int64_t kept = start[nc];
+    free(start);
+    return kept;
 }
 
-/* Rows of the truncated product for kept full ranks: the row's own index and
- * a target's index are the kept ranks below them (bits plus the exclusive
- * prefix count per word); targets outside the kept space are dropped.
- * Returns -1 if a listed rank is not kept. */
-int or_trunc_sigma_sampled(int omega, int n, const double *eps, const double *V, const uint64_t *bits,
-                           const int64_t *prefix, const int64_t *ranks, int64_t count, const double *x, double *y)
+/* Position of rank t in the ascending array a[0..len), or -1 (Sec. 3.2's
+ * binary search, over the kept states of a truncated space as in Sec. 3.5). */
+static int64_t find_rank(const int64_t *a, int64_t len, int64_t t)
+{
+    int64_t lo = 0, hi = len - 1;
+    while (lo <= hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] == t) return mid;
+        if (a[mid] < t) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* Rows of the truncated product (H restricted to the kept states) for the
+ * listed kept full ranks.  kept[0..nkept) holds the ascending full ranks of
+ * the kept states; x and the rows are indexed by position in it.  The row's
+ * own position and every hop target's are found by binary search (target
+ * full ranks from the hash); targets not kept are dropped.  Returns -1 if a
+ * listed rank is not kept. */
+int or_trunc_sigma_sampled(int omega, int n, const double *eps, const double *V, const int64_t *kept,
+                           int64_t nkept, const int64_t *ranks, int64_t count, const double *x, double *y)
 {
     int bad = 0;
     cmn_init();
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
     for (int64_t q = 0; q < count; ++q) {
         const int64_t r = ranks[q];
-        if (!((bits[r >> 6] >> (r & 63)) & 1ull)) { bad = 1; y[q] = 0.0; continue; }
-        const int64_t self = prefix[r >> 6] + __builtin_popcountll(bits[r >> 6] & ((1ull << (r & 63)) - 1ull));
+        const int64_t self = find_rank(kept, nkept, r);
+        if (self < 0) { bad = 1; y[q] = 0.0; continue; }
         const uint64_t s = or_unhash(r, n);
         double diag = 0.0;
         for (int i = 0; i < omega; ++i)
@@ -382,10 +421,9 @@ int or_trunc_sigma_sampled(int omega, int n, const double *eps, const double *V,
             if (!((s >> O) & 1ull)) continue;
             for (int E = 0; E < omega; ++E) {
                 if ((s >> E) & 1ull) continue;
-                const int64_t t = or_hash((s & ~(1ull << O)) | (1ull << E));
-                const uint64_t wd = bits[t >> 6];
-                if (!((wd >> (t & 63)) & 1ull)) continue;
-                acc += V[E * omega + O] * x[prefix[t >> 6] + __builtin_popcountll(wd & ((1ull << (t & 63)) - 1ull))];
+                const int64_t j = find_rank(kept, nkept, or_hash((s & ~(1ull << O)) | (1ull << E)));
+                if (j < 0) continue;
+                acc += V[E * omega + O] * x[j];
             }
         }
         y[q] = acc;

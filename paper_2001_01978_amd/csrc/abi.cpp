@@ -178,7 +178,7 @@ struct TruncLayout {
 TruncLayout trunc_layout(int64_t full_dim, int64_t kept) {
     TruncLayout L;
     L.W = (full_dim + 63) / 64;
-    size_t off = kCoefBytes;
+    size_t off = kHandleBlockBytes;
     L.words = off;
     off += align256((size_t)L.W * sizeof(TruncWord));
     L.kranks = off;
@@ -187,6 +187,79 @@ TruncLayout trunc_layout(int64_t full_dim, int64_t kept) {
     off += align256(trunc_scan_words(full_dim) * sizeof(uint64_t));
     L.total = off;
     return L;
+}
+
+// A handle over dev_buf (its first kHandleBlockBytes are the sigma slots) on
+// the current device, with one event per slot; nullptr (message set) on failure.
+void delete_handle(pd_basis b) {
+    if (!b) return;
+    for (int i = 0; i < kSigmaSlots; ++i)
+        if (b->slot[i].done) (void)hipEventDestroy(b->slot[i].done);
+    delete b;
+}
+
+pd_basis new_handle(void *dev_buf) {
+    pd_basis b = new (std::nothrow) pd_basis_s;
+    if (!b) {
+        set_error("host allocation failed");
+        return nullptr;
+    }
+    b->omega = b->n = 0;
+    b->dim = 0;
+    b->states = nullptr;
+    b->next_slot = 0;
+    b->truncated = 0;
+    std::memset(&b->trunc, 0, sizeof(b->trunc));
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+    for (int i = 0; i < kSigmaSlots; ++i) {
+        b->slot[i].dev = reinterpret_cast<CoefBlock *>(static_cast<unsigned char *>(dev_buf) + i * kCoefBytes);
+        hipError_t e = hipEventCreateWithFlags(&b->slot[i].done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            b->slot[i].done = nullptr;
+            set_error("hipEventCreateWithFlags: %s", hipGetErrorString(e));
+            delete_handle(b);
+            return nullptr;
+        }
+    }
+    return b;
+}
+
+// The coefficient block a pd_sigma call on `stream` uses (caller holds b->mu).
+// In order of preference: a block last used on this stream with the same
+// coefficients, any block last used on this stream, an unused block, a block
+// whose last product has finished; else the round-robin victim, after which
+// `stream` waits for that block's last product.  A block whose product is
+// still running on another stream is thus never rewritten or shared.
+pd_status acquire_slot(pd_basis b, const CoefBlock &blk, hipStream_t stream, SigmaSlot **out) {
+    SigmaSlot *same = nullptr, *idle = nullptr;
+    for (int i = 0; i < kSigmaSlots; ++i) {
+        SigmaSlot &s = b->slot[i];
+        if (s.used && s.last_stream == stream) {
+            if (s.has_coef && std::memcmp(&blk, &s.host, sizeof(CoefBlock)) == 0) {
+                *out = &s;
+                return PD_OK;
+            }
+            if (!same) same = &s;
+        }
+    }
+    if (same) {
+        *out = same;
+        return PD_OK;
+    }
+    for (int i = 0; i < kSigmaSlots && !idle; ++i)
+        if (!b->slot[i].used) idle = &b->slot[i];
+    for (int i = 0; i < kSigmaSlots && !idle; ++i) {
+        hipError_t q = hipEventQuery(b->slot[i].done);
+        if (q == hipSuccess) idle = &b->slot[i];
+        else if (q != hipErrorNotReady) return fail(PD_EDEVICE, "hipEventQuery: %s", hipGetErrorString(q));
+    }
+    if (!idle) {
+        idle = &b->slot[b->next_slot++ % kSigmaSlots];
+        hipError_t e = hipStreamWaitEvent(stream, idle->done, 0);
+        if (e != hipSuccess) return fail(PD_EDEVICE, "hipStreamWaitEvent: %s", hipGetErrorString(e));
+    }
+    *out = idle;
+    return PD_OK;
 }
 
 }  // namespace
@@ -283,7 +356,7 @@ int64_t pd_dimension(int omega, int n) {
 
 size_t pd_basis_bytes(int omega, int n, int store_states) {
     if (!valid_space(omega, n)) return 0;
-    size_t b = kCoefBytes;
+    size_t b = kHandleBlockBytes;
     if (store_states) b += align256((size_t)binom_host(omega, n) * sizeof(uint64_t));
     return b;
 }
@@ -297,22 +370,17 @@ pd_status pd_basis_create(int omega, int n, int store_states, void *dev_buf, siz
     pd_status st = check_device_ptr(dev_buf, "dev_buf", need);
     if (st != PD_OK) return st;
     if (reinterpret_cast<uintptr_t>(dev_buf) & 255) return fail(PD_EINVAL, "dev_buf must be 256-byte aligned");
-    pd_basis b = new (std::nothrow) pd_basis_s;
-    if (!b) return fail(PD_ENOMEM, "host allocation failed");
+    pd_basis b = new_handle(dev_buf);
+    if (!b) return fail(PD_EDEVICE, "handle creation: %s", last_error());
     b->omega = omega;
     b->n = n;
     b->dim = (int64_t)binom_host(omega, n);
-    b->coef = reinterpret_cast<CoefBlock *>(dev_buf);
-    b->states = store_states ? reinterpret_cast<uint64_t *>(static_cast<unsigned char *>(dev_buf) + kCoefBytes)
+    b->states = store_states ? reinterpret_cast<uint64_t *>(static_cast<unsigned char *>(dev_buf) + kHandleBlockBytes)
                              : nullptr;
-    b->has_coef = 0;
-    b->truncated = 0;
-    std::memset(&b->trunc, 0, sizeof(b->trunc));
-    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
     if (b->states) {
         hipError_t e = launch_basis_build(omega, n, b->dim, b->states, stream);
         if (e != hipSuccess) {
-            delete b;
+            delete_handle(b);
             return fail(PD_EDEVICE, "basis build: %s", hipGetErrorString(e));
         }
     }
@@ -320,7 +388,7 @@ pd_status pd_basis_create(int omega, int n, int store_states, void *dev_buf, siz
     return PD_OK;
 }
 
-void pd_basis_destroy(pd_basis b) { delete b; }
+void pd_basis_destroy(pd_basis b) { delete_handle(b); }
 
 pd_status pd_basis_info(pd_basis b, int *omega, int *n, int64_t *dim) {
     pd_status st = check_basis(b);
@@ -371,17 +439,24 @@ pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt, 
     if ((st = check_device_ptr(x_dev, "x_dev", b->dim * es)) != PD_OK) return st;
     if ((st = check_device_ptr(y_dev, "y_dev", b->dim * es)) != PD_OK) return st;
     if (overlap(x_dev, b->dim * es, y_dev, b->dim * es)) return fail(PD_EINVAL, "x and y overlap");
+    std::lock_guard<std::mutex> lock(b->mu);
+    SigmaSlot *sl = nullptr;
+    if ((st = acquire_slot(b, blk, stream, &sl)) != PD_OK) return st;
     // Upload only when the coefficients change; the copy completes before returning.
-    if (!b->has_coef || std::memcmp(&blk, &b->host_coef, sizeof(CoefBlock)) != 0) {
-        hipError_t e = hipMemcpyAsync(b->coef, &blk, sizeof(CoefBlock), hipMemcpyHostToDevice, stream);
+    if (!sl->has_coef || std::memcmp(&blk, &sl->host, sizeof(CoefBlock)) != 0) {
+        sl->host = blk;
+        sl->has_coef = 0;
+        hipError_t e = hipMemcpyAsync(sl->dev, &sl->host, sizeof(CoefBlock), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return fail(PD_EDEVICE, "coefficient upload: %s", hipGetErrorString(e));
-        b->host_coef = blk;
-        b->has_coef = 1;
+        sl->has_coef = 1;
     }
-    hipError_t e = launch_sigma(b->omega, b->n, b->dim, b->coef, dt, x_dev, y_dev, stream, blk.dsum64, blk.dsum32,
+    hipError_t e = launch_sigma(b->omega, b->n, b->dim, sl->dev, dt, x_dev, y_dev, stream, blk.dsum64, blk.dsum32,
                                 trunc_of(b));
+    if (e == hipSuccess) e = hipEventRecord(sl->done, stream);
     if (e != hipSuccess) return fail(PD_EDEVICE, "sigma: %s", hipGetErrorString(e));
+    sl->used = 1;
+    sl->last_stream = stream;
     return PD_OK;
 }
 
@@ -476,21 +551,18 @@ pd_status pd_basis_create_truncated(int omega, int n, const double *eps, const d
     const int64_t built = (int64_t)(last.base + (uint64_t)__builtin_popcountll(last.bits));
     if (built != info->kept)
         return fail(PD_EINVAL, "selection keeps %lld states, info says %lld", (long long)built, (long long)info->kept);
-    pd_basis b = new (std::nothrow) pd_basis_s;
-    if (!b) return fail(PD_ENOMEM, "host allocation failed");
+    pd_basis b = new_handle(dev_buf);
+    if (!b) return fail(PD_EDEVICE, "handle creation: %s", last_error());
     b->omega = omega;
     b->n = n;
     b->dim = info->kept;
     b->states = nullptr;
-    b->coef = reinterpret_cast<CoefBlock *>(dev_buf);
-    b->has_coef = 0;
     b->truncated = 1;
     b->trunc.full_dim = full_dim;
     b->trunc.kept = info->kept;
     b->trunc.kranks = kranks;
     b->trunc.words = words;
     b->trunc.index_mode = index_mode == PD_TRUNC_BSEARCH ? kTruncBsearch : kTruncBitmap;
-    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
     *out = b;
     return PD_OK;
 }
@@ -745,6 +817,35 @@ pd_status pd_mlp_adam(int64_t count, float *params_dev, const float *grads_dev, 
     if ((st = check_device_ptr(v_dev, "v_dev", count * 4)) != PD_OK) return st;
     hipError_t e = launch_adam((int)count, params_dev, grads_dev, m_dev, v_dev, lr, beta1, beta2, eps, step, stream);
     if (e != hipSuccess) return fail(PD_EDEVICE, "adam: %s", hipGetErrorString(e));
+    return PD_OK;
+}
+
+int64_t pd_stream_probe_bytes(int kind, int64_t n) {
+    if (n <= 0) return 0;
+    switch (kind & ~PD_PROBE_NONTEMPORAL) {
+        case PD_PROBE_READ: return 4 * n;
+        case PD_PROBE_COPY: return 8 * n;
+        case PD_PROBE_TRIAD: return 12 * n;
+        case PD_PROBE_WRITE: return 4 * n;
+    }
+    return 0;
+}
+
+pd_status pd_stream_probe(int kind, const float *a_dev, const float *b_dev, float *c_dev, int64_t n,
+                          hipStream_t stream) {
+    const int k = kind & ~PD_PROBE_NONTEMPORAL;
+    if (k < PD_PROBE_READ || k > PD_PROBE_WRITE) return fail(PD_EINVAL, "probe kind %d", kind);
+    if (n <= 0 || n % 1024) return fail(PD_EINVAL, "n=%lld is not a positive multiple of 1024", (long long)n);
+    const size_t nb = (size_t)n * 4;
+    pd_status st;
+    if (k != PD_PROBE_WRITE && (st = check_device_ptr(a_dev, "a_dev", nb)) != PD_OK) return st;
+    if (k == PD_PROBE_TRIAD && (st = check_device_ptr(b_dev, "b_dev", nb)) != PD_OK) return st;
+    if ((st = check_device_ptr(c_dev, "c_dev", k == PD_PROBE_READ ? (size_t)probe_grid(n) * 4 : nb)) != PD_OK)
+        return st;
+    if (k != PD_PROBE_WRITE && overlap(a_dev, nb, c_dev, nb)) return fail(PD_EINVAL, "c overlaps a");
+    if (k == PD_PROBE_TRIAD && overlap(b_dev, nb, c_dev, nb)) return fail(PD_EINVAL, "c overlaps b");
+    hipError_t e = launch_stream_probe(k, (kind & PD_PROBE_NONTEMPORAL) != 0, a_dev, b_dev, c_dev, n, stream);
+    if (e != hipSuccess) return fail(PD_EDEVICE, "stream probe: %s", hipGetErrorString(e));
     return PD_OK;
 }
 

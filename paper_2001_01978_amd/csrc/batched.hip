@@ -796,26 +796,38 @@ pd_status batched_run(int count, const int *omega, const int *n, const double *e
             const int trial_grid = As.teams ? L.grid : std::min(S, L.grid);
             double best = 1e300;
             const int cands[3] = {128, 256, 512};
-            hipEvent_t e0, e1;
-            PD_HIP(hipEventCreate(&e0));
-            PD_HIP(hipEventCreate(&e1));
+            struct Events {
+                hipEvent_t a = nullptr, b = nullptr;
+                ~Events() {
+                    if (a) (void)hipEventDestroy(a);
+                    if (b) (void)hipEventDestroy(b);
+                }
+            } ev;
+            PD_HIP(hipEventCreate(&ev.a));
+            PD_HIP(hipEventCreate(&ev.b));
+            block = 0;
             for (int c : cands) {
                 hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, stream, d_counter, As.n_large, d_large,
                                    d_team_ctl, kCtlInts * 8, d_error);
-                PD_HIP(hipEventRecord(e0, stream));
+                PD_HIP(hipEventRecord(ev.a, stream));
                 hipLaunchKernelGGL(batched_kernel, dim3(trial_grid), dim3(c), batched_dyn_lds(c), stream, As);
                 PD_HIP(hipGetLastError());
-                PD_HIP(hipEventRecord(e1, stream));
-                PD_HIP(hipEventSynchronize(e1));
+                PD_HIP(hipEventRecord(ev.b, stream));
+                PD_HIP(hipEventSynchronize(ev.b));
                 float ms = 0.0f;
-                PD_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
+                PD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                // A trial whose team barrier timed out drained early: its time
+                // means nothing, so the candidate is not eligible.
+                int trial_err = 0;
+                PD_HIP(hipMemcpy(&trial_err, d_error, sizeof(int), hipMemcpyDeviceToHost));
+                if (!trial_err && ms < best) {
                     best = ms;
                     block = c;
                 }
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
+            if (block == 0)
+                return fail(PD_EDEVICE, "every autotuner trial hit a team barrier time-out (is another kernel "
+                                        "occupying the GPU?)");
             g_tuned[key] = block;
             tuned = 1;
             tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <cstddef>
+#include <mutex>
 
 #include "pairdiag.h"
 
@@ -50,6 +51,13 @@ struct CoefBlock {
 };
 constexpr size_t kCoefBytes = (sizeof(CoefBlock) + 255) & ~size_t(255);
 
+// A basis handle carries kSigmaSlots coefficient blocks for pd_sigma, so
+// products on several streams can use one handle at once: a call takes a
+// block that is idle, or last used on its own stream (stream order protects
+// it), and otherwise makes its stream wait for the block's last product.
+constexpr int kSigmaSlots = 4;
+constexpr size_t kHandleBlockBytes = kSigmaSlots * kCoefBytes;
+
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------- errors
@@ -91,15 +99,27 @@ inline bool trunc_ranks32(int64_t full_dim) { return full_dim < (int64_t(1) << 3
 
 }  // namespace pd
 
+namespace pd {
+// One coefficient block of a handle and what the host knows of its use.
+struct SigmaSlot {
+    CoefBlock *dev = nullptr;       // device block (coefficients + tile counters)
+    CoefBlock host;                 // what dev holds, when has_coef
+    int has_coef = 0;
+    int used = 0;                   // a product has been issued on it
+    hipStream_t last_stream = nullptr;
+    hipEvent_t done = nullptr;      // recorded after its last product
+};
+}  // namespace pd
+
 struct pd_basis_s {
     int omega;
     int n;
     int64_t dim;
     uint64_t *states;        // device, dim entries, or nullptr
-    pd::CoefBlock *coef;     // device, per-handle block for pd_sigma
     int device;
-    int has_coef;            // coef holds host_coef
-    pd::CoefBlock host_coef; // last block uploaded by pd_sigma
+    pd::SigmaSlot slot[pd::kSigmaSlots];
+    unsigned next_slot;      // round-robin victim when every slot is busy elsewhere
+    std::mutex mu;           // guards slot[] and next_slot (pd_sigma from several threads)
     int truncated;           // 1: dim = trunc.kept rows of a truncated space
     pd::TruncSpace trunc;
 };
@@ -216,6 +236,12 @@ hipError_t launch_adam(int count, float *p, const float *g, float *m, float *v, 
                        float eps, int step, hipStream_t s);
 hipError_t launch_warm_expand(int omega, int n, int64_t dim, const float *logits, double lmax, double *psi,
                               hipStream_t s);
+
+// probe.hip: streaming kernels of known byte count (achievable HBM bandwidth).
+constexpr int kProbeMaxGrid = 2048;
+int probe_grid(int64_t n);
+hipError_t launch_stream_probe(int kind, bool nontemporal, const float *a, const float *b, float *c, int64_t n,
+                               hipStream_t s);
 
 // tridiag.cpp: lowest eigenpair of the symmetric tridiagonal (alpha, beta).
 int tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y);

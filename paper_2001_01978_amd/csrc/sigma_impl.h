@@ -86,13 +86,13 @@ __device__ __forceinline__ void stage_tables(unsigned char *smem, int omega, int
 }
 
 template <typename R, typename T>
-__host__ __device__ inline size_t table_bytes(int omega, int ks) {
+__host__ __device__ constexpr size_t table_bytes(int omega, int ks) {
     return (((size_t)omega * ks * sizeof(R) + 15) & ~size_t(15)) + ((size_t)omega * omega + omega) * sizeof(T);
 }
 
 // Per-lane LDS scratch of sigma_row: 2 (NN + 1) rank words per thread.
 template <typename R>
-__host__ __device__ inline size_t prefix_bytes(int nn, int block) {
+__host__ __device__ constexpr size_t prefix_bytes(int nn, int block) {
     return (size_t)(2 * nn + 2) * block * sizeof(R);
 }
 
@@ -327,18 +327,25 @@ __global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
     }
 }
 
+// Dynamic LDS limit to set on an instantiation with NN pairs and BLOCK
+// threads: the most any omega <= 62 can ask of it (tables plus per-lane
+// slots), capped at what a CU holds.  One value per instantiation, so calls
+// with different omegas, in any order and from any thread, agree on it.
+template <typename R, typename T, int NN, int BLOCK>
+constexpr size_t lds_limit() {
+    const size_t need = ((table_bytes<R, T>(kMaxOmega, NN + 2) + 15) & ~size_t(15)) + prefix_bytes<R>(NN, BLOCK);
+    return need < kLdsPerCU - 1024 ? need : kLdsPerCU - 1024;
+}
+
 template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
 hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
     // More than the default 64 KB of dynamic LDS needs the attribute.
     if (smem > 64 * 1024) {
-        static bool raised = false;
-        if (!raised) {
-            hipError_t e =
-                hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP, BLOCK, BUF>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-            if (e != hipSuccess) return e;
-            raised = true;
-        }
+        constexpr size_t lim = lds_limit<R, T, NN, BLOCK>();
+        if (smem > lim) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sigma_kernel<R, T, NN, COMP, BLOCK, BUF>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
+        if (e != hipSuccess) return e;
     }
     P.ntiles = (P.dim + BLOCK - 1) / BLOCK;
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
@@ -422,7 +429,9 @@ hipError_t launch_trunc_nn(TruncParams<R, T> Q, int mode, hipStream_t stream) {
     const void *fn = mode == kTruncBsearch ? reinterpret_cast<const void *>(&sigma_trunc_kernel<R, T, NN, COMP, B, 2>)
                                            : reinterpret_cast<const void *>(&sigma_trunc_kernel<R, T, NN, COMP, B, 1>);
     if (smem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        constexpr size_t lim = lds_limit<R, T, NN, B>();
+        if (smem > lim) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim);
         if (e != hipSuccess) return e;
     }
     Q.P.ntiles = (Q.kept + B - 1) / B;

@@ -119,6 +119,8 @@ SIGNATURES = {
     "pd_batched_workspace_bytes": (SZ, [I, P, P, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_ground_batched": (I, [I, P, P, P, P, ctypes.POINTER(LanczosOpts), I, P, SZ, P, P,
                                       ctypes.POINTER(LanczosInfo), ctypes.POINTER(BatchInfo), P]),
+    "pd_stream_probe_bytes": (I64, [I, I64]),
+    "pd_stream_probe": (I, [I, P, P, P, I64, P]),
 }
 
 _lib = None
@@ -182,6 +184,22 @@ def device_buffer(nbytes: int, device="cuda"):
     t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
     off = (-t.data_ptr()) % 256
     return t, off
+
+
+PROBE = {"read": 0, "copy": 1, "triad": 2, "write": 3}
+PD_PROBE_NONTEMPORAL = 16
+
+
+def stream_probe(kind: str, a, b, c, nontemporal=False, stream=None) -> int:
+    """One launch of the library's streaming kernel `kind` over float32 device
+    tensors of equal length (pd_stream_probe); returns the bytes it moves.
+    a is unused by 'write', b is used by 'triad' only (None allowed)."""
+    L = load()
+    k = PROBE[kind] | (PD_PROBE_NONTEMPORAL if nontemporal else 0)
+    n = c.numel()
+    _check(L.pd_stream_probe(k, _dptr(a) if a is not None else None, _dptr(b) if b is not None else None, _dptr(c),
+                             n, _stream(stream)))
+    return int(L.pd_stream_probe_bytes(k, n))
 
 
 def dimension(omega: int, n: int) -> int:

@@ -111,6 +111,19 @@ class WarmNet:
                                              pdg._stream(None)))
         return out
 
+    def forward_first_layer(self, X):
+        """Logits, and the first layer's pre-activations Z1 = X W1 + b1 (B x h1)
+        that pd_mlp_forward leaves at the start of its workspace."""
+        import torch
+        B = X.shape[0]
+        (buf, off), nb = self._work(B)
+        out = torch.empty(B, self.omega, dtype=torch.float32, device=self.device)
+        pdg._check(pdg.load().pd_mlp_forward(ctypes.byref(self.shape), pdg._dptr(self.params), pdg._dptr(X), B,
+                                             ctypes.c_void_p(buf.data_ptr() + off), nb, pdg._dptr(out),
+                                             pdg._stream(None)))
+        z1 = buf[off: off + 4 * B * self.shape.h1].view(torch.float32).reshape(B, self.shape.h1).clone()
+        return out, z1
+
     def gradients(self, X, T):
         """(grads, loss) of the mean squared error of sigmoid(logits) against T."""
         import torch

@@ -1,0 +1,149 @@
+"""GPU: products on several streams and host threads sharing one basis handle,
+launch limits that depend on the call order, and the streaming kernels the
+bandwidth figures are measured with.
+
+Products use dyadic inputs (every product and partial sum exact), so each
+result is compared with the oracle bit for bit whatever the summation order.
+"""
+import math
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2001_01978_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pdg():
+    from paper_2001_01978_amd import pairdiag
+    pairdiag.load()
+    return pairdiag
+
+
+def _case(oracle_mod, om, n, seed):
+    _, _, eps, V = inputs.dyadic_instance(om, n, seed=seed)
+    d = math.comb(om, n)
+    x = inputs.dyadic_vector(seed + 1, d, bits=6)
+    want = oracle_mod.sigma(om, n, eps, V, oracle_mod.basis_alg1(om, n), x)
+    return eps, V, x, want
+
+
+def test_sigma_two_streams_one_handle(torch_cuda, pdg, oracle_mod):
+    """Omega=24, n=12 (2.7e6 states, 5282 tiles per product through the
+    per-XCD tile counters): products issued alternately on two streams with
+    two different coefficient sets, nothing synchronised between them, more
+    products in flight than the handle has coefficient blocks."""
+    torch = torch_cuda
+    om, n = 24, 12
+    cases = [_case(oracle_mod, om, n, s) for s in (21, 22)]
+    b = pdg.Basis(om, n, store_states=False)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for dt in (torch.float64, torch.float32):
+        xs = [torch.tensor(c[2], dtype=dt, device="cuda") for c in cases]
+        torch.cuda.synchronize()
+        ys = []
+        for k in range(12):
+            j = k % 2
+            eps, V, _, _ = cases[j]
+            with torch.cuda.stream(streams[j]):
+                y = torch.full_like(xs[j], float("nan"))
+                b.sigma(eps, V, xs[j], y, stream=streams[j])
+                ys.append((j, y))
+        torch.cuda.synchronize()
+        for j, y in ys:
+            assert np.array_equal(y.cpu().numpy().astype(np.float64), cases[j][3]), (dt, j)
+
+
+def test_sigma_threads_one_handle(torch_cuda, pdg, oracle_mod):
+    """Four host threads, each on its own stream with its own coefficients,
+    issue products on one handle at the same time."""
+    torch = torch_cuda
+    om, n = 22, 11
+    cases = [_case(oracle_mod, om, n, s) for s in (31, 32, 33, 34)]
+    b = pdg.Basis(om, n, store_states=False)
+    results, errors = {}, []
+
+    def work(j):
+        try:
+            st = torch.cuda.Stream()
+            eps, V, x, _ = cases[j]
+            with torch.cuda.stream(st):
+                xt = torch.tensor(x, device="cuda")
+                out = []
+                for _ in range(6):
+                    y = torch.full_like(xt, float("nan"))
+                    b.sigma(eps, V, xt, y, stream=st)
+                    out.append(y)
+            st.synchronize()
+            results[j] = [y.cpu().numpy() for y in out]
+        except Exception as e:      # reported by the main thread
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(j,)) for j in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for j in range(4):
+        for y in results[j]:
+            assert np.array_equal(y, cases[j][3]), j
+
+
+def test_sigma_lds_limit_any_omega_order(torch_cuda, pdg, oracle_mod):
+    """One kernel instantiation (FP64, 14 pairs, 512 threads) serves Omega=28
+    and Omega=29; both need more than 64 KB of LDS, the larger space more
+    than the smaller.  Run the smaller first, then the larger, then the
+    smaller again: every product exact on sampled rows."""
+    torch = torch_cuda
+    for om in (28, 29, 28):
+        n = 14
+        _, _, eps, V = inputs.dyadic_instance(om, n, seed=om)
+        d = math.comb(om, n)
+        b = pdg.Basis(om, n, store_states=False)
+        x = torch.randint(-63, 64, (d,), dtype=torch.float64, device="cuda")
+        y = b.sigma(eps, V, x)
+        rng = np.random.default_rng(om)
+        rows = np.unique(np.concatenate([rng.integers(0, d, 3000), [0, d - 1]]))
+        diag, tg, cf = oracle_mod.row_terms(om, n, eps, V, rows)
+        xh = x.cpu().numpy()
+        want = diag * xh[rows] + (cf * xh[tg]).sum(axis=1)
+        got = y[torch.tensor(rows, device="cuda")].cpu().numpy()
+        assert np.array_equal(got, want), om
+        del x, y
+
+
+@pytest.mark.parametrize("nontemporal", [False, True])
+def test_stream_probe_kernels(torch_cuda, pdg, nontemporal):
+    """Each streaming kernel computes what it claims on every element (so the
+    bytes it is credited with are really moved)."""
+    torch = torch_cuda
+    n = (1 << 22) + 3 * 1024          # not a multiple of the grid's stride
+    a = torch.arange(n, dtype=torch.float32, device="cuda") % 1000
+    b = torch.full((n,), 4.0, dtype=torch.float32, device="cuda")
+    c = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    assert pdg.stream_probe("copy", a, None, c, nontemporal) == 8 * n
+    assert torch.equal(c, a)
+    assert pdg.stream_probe("triad", a, b, c, nontemporal) == 12 * n
+    assert torch.equal(c, a + 2.0)
+    assert pdg.stream_probe("write", None, None, c, nontemporal) == 4 * n
+    assert torch.all(c == 0.5)
+    c.fill_(0.0)
+    ones = torch.ones(n, dtype=torch.float32, device="cuda")
+    assert pdg.stream_probe("read", ones, None, c, nontemporal) == 4 * n
+    torch.cuda.synchronize()
+    assert float(c.double().sum()) == float(n)      # partial sums of ones are exact
+    with pytest.raises(pdg.PairDiagError):
+        pdg.stream_probe("copy", a[:1000], None, c[:1000], nontemporal)      # n not a multiple of 1024
+    with pytest.raises(pdg.PairDiagError):
+        pdg.stream_probe("copy", a, None, a, nontemporal)                    # c overlaps a

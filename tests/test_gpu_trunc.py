@@ -165,22 +165,20 @@ def test_full_size_cut_kept_set_and_sampled_rows(pdg, oracle_mod):
     ref = oracle_mod.trunc_select(om, n, eps, V, limit, bins, method="c")
     _check_select(info, ref)
     print("trunc full size: kept set", flush=True)
-    bits, prefix = oracle_mod.trunc_bits(om, n, eps, V, ref, bins)
+    kept = oracle_mod.trunc_kept_ranks(om, n, eps, V, ref, bins)
     b = pdg.Basis.truncated(om, n, eps, V, limit, bins, info=info)
     kr = b.kept_ranks().cpu().numpy()
     assert kr.size == ref["kept"]
-    flags = np.zeros(bits.size * 64, dtype=bool)
-    flags[kr] = True
-    np.testing.assert_array_equal(np.packbits(flags, bitorder="little").view(np.uint64), bits)
-    del flags, kr
+    np.testing.assert_array_equal(kr, kept)
+    del kr
     print("trunc full size: sampled rows", flush=True)
+    # rows drawn by position in the oracle's kept list: the position is the
+    # row index, the entry its full rank
     rng = np.random.default_rng(11)
-    cand = rng.integers(0, ref["full_dim"], 40000)
-    rows = np.unique(cand[((bits[cand >> 6] >> (cand & 63).astype(np.uint64)) & np.uint64(1)).astype(bool)])[:3000]
-    idx = prefix[rows >> 6] + np.bitwise_count(bits[rows >> 6] & ((np.uint64(1) << (rows & 63).astype(np.uint64))
-                                                                  - np.uint64(1))).astype(np.int64)
+    idx = np.unique(np.concatenate([rng.integers(0, kept.size, 3000), [0, kept.size - 1]]))
+    rows = kept[idx]
     x = inputs.random_vector(7, b.dim)
-    y_ref = oracle_mod.trunc_sigma_sampled(om, n, eps, V, bits, prefix, rows, x)
+    y_ref = oracle_mod.trunc_sigma_sampled(om, n, eps, V, kept, rows, x)
     scale = (2 * np.abs(eps).max() + np.abs(V).sum(axis=1).max()) * n * (om - n)
     y = b.sigma(eps, V, torch.tensor(x, device="cuda"))[torch.tensor(idx, device="cuda")].cpu().numpy()
     assert np.abs(y - y_ref).max() <= 1e-13 * scale

@@ -37,14 +37,24 @@ def test_forward_matches_oracle(mods, oracle_mod, omega, batch, hidden):
     p += np.random.default_rng(1).normal(0, 0.05, p.size).astype(np.float32)
     net.params = torch.tensor(p, device="cuda")
     X = np.random.default_rng(2).normal(size=(batch, warm.n_features(omega))).astype(np.float32)
-    got = net.forward(torch.tensor(X, device="cuda")).cpu().numpy().astype(np.float64)
+    logits, z1 = net.forward_first_layer(torch.tensor(X, device="cuda"))
+    got = logits.cpu().numpy().astype(np.float64)
     want, _ = oracle_mod.mlp_forward(net.param_arrays(), X.astype(np.float64))
-    err = np.abs(got - want).max() / max(np.abs(want).max(), 1e-3)
-    assert err < 3e-2, err
-    # exact check of the first layer's rounding model: BF16 operands, FP32 accumulation
-    W1, b1 = net.param_arrays()[:2]
-    z1 = _bf16(X) @ _bf16(W1) + b1
-    assert np.isfinite(z1).all()
+    # three BF16 layers (operands rounded to 8-bit mantissas) against FP64:
+    # every logit within 1e-2 of the largest one
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err < 1e-2, err
+    # The first layer's rounding model, element by element: operands rounded to
+    # BF16 (their products are exact in FP32), sums accumulated in FP32.  With
+    # K = in terms, any FP32 summation order stays within (K + 1) 2^-24 of the
+    # sum of magnitudes; the FP64 sum of the rounded operands is the reference.
+    W1, b1 = [np.asarray(a, np.float64) for a in net.param_arrays()[:2]]
+    ref = _bf16(X) @ _bf16(W1) + b1
+    mag = np.abs(_bf16(X)) @ np.abs(_bf16(W1)) + np.abs(b1)
+    K = X.shape[1]
+    z1 = z1.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(z1 - ref) <= (K + 1) * 2.0 ** -24 * mag), np.abs(z1 - ref).max()
+    assert np.abs(z1 - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
 def test_gradients_match_oracle(mods, oracle_mod):
@@ -60,11 +70,15 @@ def test_gradients_match_oracle(mods, oracle_mod):
     l64, dout = oracle_mod.mlp_loss(out, T)
     want = np.concatenate([a.reshape(-1) for a in oracle_mod.mlp_backward(params, cache, dout)])
     got = g.cpu().numpy().astype(np.float64)
-    assert abs(float(loss.item()) - l64) <= 2e-2 * abs(l64)
-    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
-    assert rel < 3e-2, rel
-    cos = got @ want / (np.linalg.norm(got) * np.linalg.norm(want))
-    assert cos > 0.999
+    assert abs(float(loss.item()) - l64) <= 1e-2 * abs(l64)
+    # element by element, per parameter block (W1, b1, W2, b2, W3, b3): within
+    # 1e-2 of the block's largest FP64 gradient
+    o = 0
+    for name, a in zip(["W1", "b1", "W2", "b2", "W3", "b3"], params):
+        w = want[o:o + a.size]
+        e = np.abs(got[o:o + a.size] - w).max() / np.abs(w).max()
+        assert e < 1e-2, (name, e)
+        o += a.size
 
 
 def test_adam_matches_formula(mods):

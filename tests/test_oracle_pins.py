@@ -65,6 +65,23 @@ def test_alg1_walkthrough(oracle_mod, golden_dir):
         assert s == want
 
 
+def test_successor_is_next_integer_with_equal_popcount(oracle_mod):
+    # The successor's definition checked by exhaustive search: for every
+    # s < 2^13 with at least one set bit, the smallest t > s with as many ones.
+    nxt = {}
+    by_count = {}
+    for t in range(1, 1 << 14):
+        by_count.setdefault(bin(t).count("1"), []).append(t)
+    for k, ts in by_count.items():
+        for a, b in zip(ts, ts[1:]):
+            nxt[a] = b
+    for s in range(1, 1 << 13):
+        assert oracle_mod.next_state(s) == nxt[s], s
+    # near the top of a 62-orbit space
+    top = ((1 << 5) - 1) << 56
+    assert oracle_mod.next_state(top) == (1 << 61) | ((1 << 4) - 1)
+
+
 @pytest.mark.parametrize("omega", range(1, 15))
 def test_basis_brute_force(oracle_mod, omega):
     # all n-subsets of omega orbits as bitmasks, sorted ascending

@@ -125,12 +125,11 @@ def test_c_histogram_path_matches_numpy_path(oracle_mod, omega, n, limit, bins):
     c = oracle_mod.trunc_select(omega, n, eps, V, limit, bins, method="c")
     for k in ("full_dim", "kept", "cut_bin", "dmin", "dmax", "scale"):
         assert a[k] == c[k], k
-    bits, prefix = oracle_mod.trunc_bits(omega, n, eps, V, c, bins)
-    keep = np.unpackbits(bits.view(np.uint8), bitorder="little")[: a["full_dim"]].astype(bool)
-    np.testing.assert_array_equal(np.nonzero(keep)[0], a["ranks"])
+    kept = oracle_mod.trunc_kept_ranks(omega, n, eps, V, c, bins)
+    np.testing.assert_array_equal(kept, a["ranks"])
     x = np.random.default_rng(1).standard_normal(a["kept"])
     rows = a["ranks"][:: max(1, a["kept"] // 300)]
-    y = oracle_mod.trunc_sigma_sampled(omega, n, eps, V, bits, prefix, rows, x)
+    y = oracle_mod.trunc_sigma_sampled(omega, n, eps, V, kept, rows, x)
     y_all = oracle_mod.sigma(omega, n, eps, V, a["states"], x, index_mode="bsearch_truncated")
     idx = np.searchsorted(a["ranks"], rows)
     np.testing.assert_allclose(y, y_all[idx], rtol=1e-13, atol=1e-12)
