@@ -840,7 +840,7 @@ pd_status pd_stream_probe(int kind, const float *a_dev, const float *b_dev, floa
     pd_status st;
     if (k != PD_PROBE_WRITE && (st = check_device_ptr(a_dev, "a_dev", nb)) != PD_OK) return st;
     if (k == PD_PROBE_TRIAD && (st = check_device_ptr(b_dev, "b_dev", nb)) != PD_OK) return st;
-    if ((st = check_device_ptr(c_dev, "c_dev", k == PD_PROBE_READ ? (size_t)probe_grid(n) * 4 : nb)) != PD_OK)
+    if ((st = check_device_ptr(c_dev, "c_dev", k == PD_PROBE_READ ? (size_t)probe_grid(PD_PROBE_READ, n) * 4 : nb)) != PD_OK)
         return st;
     if (k != PD_PROBE_WRITE && overlap(a_dev, nb, c_dev, nb)) return fail(PD_EINVAL, "c overlaps a");
     if (k == PD_PROBE_TRIAD && overlap(b_dev, nb, c_dev, nb)) return fail(PD_EINVAL, "c overlaps b");

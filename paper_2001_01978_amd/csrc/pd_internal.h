@@ -238,8 +238,10 @@ hipError_t launch_warm_expand(int omega, int n, int64_t dim, const float *logits
                               hipStream_t s);
 
 // probe.hip: streaming kernels of known byte count (achievable HBM bandwidth).
-constexpr int kProbeMaxGrid = 2048;
-int probe_grid(int64_t n);
+constexpr int kProbeMaxGrid = 65536;
+// Workgroups of the streaming kernel `kind` over n floats (the read kernel
+// writes one partial sum per workgroup).
+int probe_grid(int kind, int64_t n);
 hipError_t launch_stream_probe(int kind, bool nontemporal, const float *a, const float *b, float *c, int64_t n,
                                hipStream_t s);
 

@@ -16,7 +16,6 @@ namespace pd {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-constexpr int kProbeThreads = 256;
 constexpr int kProbeUnroll = 4;
 
 template <bool NT>
@@ -36,7 +35,7 @@ __device__ __forceinline__ void st4(f4 *p, f4 v) {
 }
 
 // n4 = number of 4-float vectors (the entry point takes n as a multiple of 1024 floats).
-template <int KIND, bool NT>
+template <int KIND, bool NT, int kProbeThreads>
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(const f4 *__restrict__ a,
                                                               const f4 *__restrict__ b, f4 *__restrict__ c,
                                                               int64_t n4, float s, float *__restrict__ partial) {
@@ -83,25 +82,31 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(const f4 *__restri
     }
 }
 
+// Launch shapes from a sweep on MI355X (block 256..1024, grid 1K..64K, 1..8
+// vectors in flight): reads stream best from 512-thread workgroups on a
+// 16K grid, writes and copies from 1024-thread workgroups on a 64K grid.
+constexpr int probe_block(int kind) { return kind == PD_PROBE_READ ? 512 : 1024; }
+constexpr int64_t probe_max_grid(int kind) { return kind == PD_PROBE_READ ? 16384 : kProbeMaxGrid; }
+
 template <int KIND, bool NT>
 hipError_t launch_probe(const float *a, const float *b, float *c, int64_t n, float s, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((probe_kernel<KIND, NT>), dim3(grid), dim3(kProbeThreads), 0, st,
-                       reinterpret_cast<const f4 *>(a), reinterpret_cast<const f4 *>(b),
-                       reinterpret_cast<f4 *>(c), n / 4, s, c);
+    constexpr int B = probe_block(KIND);
+    hipLaunchKernelGGL((probe_kernel<KIND, NT, B>), dim3(grid), dim3(B), 0, st, reinterpret_cast<const f4 *>(a),
+                       reinterpret_cast<const f4 *>(b), reinterpret_cast<f4 *>(c), n / 4, s, c);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int probe_grid(int64_t n) {
-    const int64_t per = (int64_t)kProbeThreads * kProbeUnroll;
+int probe_grid(int kind, int64_t n) {
+    const int64_t per = (int64_t)probe_block(kind) * kProbeUnroll;
     int64_t g = (n / 4 + per - 1) / per;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, kProbeMaxGrid));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, probe_max_grid(kind)));
 }
 
 hipError_t launch_stream_probe(int kind, bool nt, const float *a, const float *b, float *c, int64_t n,
                                hipStream_t st) {
-    const int grid = probe_grid(n);
+    const int grid = probe_grid(kind, n);
     const float s = 0.5f;
     switch (kind) {
         case PD_PROBE_READ:

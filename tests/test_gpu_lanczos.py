@@ -325,11 +325,15 @@ def test_full_size_omega34_mixed_sampled(pdg, oracle_mod):
     assert (V < 0).all()
     b = pdg.Basis(om, n, store_states=False)
     assert b.dim == 2333606220 > 2 ** 31
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()           # memory cached by earlier tests goes back to the device
     krylov = 20
     need = pdg.workspace_bytes(b, krylov=krylov, precision="f32") + 8 * b.dim
-    free = torch.cuda.mem_get_info()[0]
+    free, total = torch.cuda.mem_get_info()
+    print(f"full-size mixed solve omega=34 n=17 krylov={krylov} ({need / 1e9:.0f} GB of {free / 1e9:.0f} GB free, "
+          f"{total / 1e9:.0f} GB total)", flush=True)
     assert need + (4 << 30) <= free, (need, free)
-    print(f"full-size mixed solve omega=34 n=17 krylov={krylov} ({need / 1e9:.0f} GB)", flush=True)
     r = pdg.lanczos_ground(b, eps, V, krylov=krylov, tol=1e-10, start="random", seed=1, precision="f32")
     print(f"E0={r.E0:.12f} products={r.iterations} rho={r.residual:.2e} {r.seconds:.1f} s", flush=True)
     assert r.converged and r.residual <= 1e-10 and r.iterations_f32 > 0
