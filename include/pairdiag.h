@@ -232,6 +232,25 @@ pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V,
                             const double *x0_dev, double *E0, double *psi0_dev, double *occ,
                             pd_lanczos_info *info, hipStream_t stream);
 
+/* pd_lanczos_ground without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The workspace is a static device array
+ * of PD_STATIC_SCRATCH_BYTES (256 MiB) inside the library, one per GPU, held
+ * until the process ends.  The call allocates nothing (no device memory, no
+ * events: info->sigma_seconds_f64/_f32 stay 0).  A problem whose
+ * pd_lanczos_workspace_bytes exceeds the array returns PD_ERANGE before any
+ * device work.  Every call on a GPU shares that GPU's array and leaves its
+ * contents behind; the solver writes every part it reads first.  Calls
+ * that overlap on one GPU would race on it: within this process a lock
+ * serialises them (each call synchronises its stream before returning);
+ * overlapping calls from other code that writes the array are not allowed.
+ * psi0_dev must not point into the array.  Arguments, outputs and the other
+ * errors as pd_lanczos_ground.  Synchronises `stream`. */
+#define PD_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+pd_status pd_lanczos_ground_static(pd_basis b, const double *eps, const double *V, const pd_lanczos_opts *o,
+                                   const double *x0_dev, double *E0, double *psi0_dev, double *occ,
+                                   pd_lanczos_info *info, hipStream_t stream);
+
 /* The nev lowest eigenpairs (the paper's "first few states", Sec. 3.4) by
  * thick-restart Lanczos, FP64: each cycle extends the kept Ritz vectors by
  * Krylov steps (the step of pd_lanczos_ground: recurrence subtracted, one

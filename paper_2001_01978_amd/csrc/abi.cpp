@@ -74,7 +74,7 @@ pd_status lanczos_eigs_run(pd_basis b, const CoefBlock &host_coef, int nev, cons
                            pd_lanczos_info *info_out, hipStream_t s);
 pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_opts *o, void *work,
                       size_t work_bytes, const double *x0, double *E0_out, double *psi0, double *occ_out,
-                      pd_lanczos_info *info_out, hipStream_t s);
+                      pd_lanczos_info *info_out, hipStream_t s, bool time_products = true);
 
 namespace {
 
@@ -637,6 +637,37 @@ pd_status pd_lanczos_ground(pd_basis b, const double *eps, const double *V, cons
         if (overlap(psi0_dev, b->dim * 8, work_dev, work_bytes)) return fail(PD_EINVAL, "psi0 overlaps workspace");
     }
     return lanczos_run(b, blk, o, work_dev, work_bytes, x0_dev, E0, psi0_dev, occ, info, stream);
+}
+
+pd_status pd_lanczos_ground_static(pd_basis b, const double *eps, const double *V, const pd_lanczos_opts *o,
+                                   const double *x0_dev, double *E0, double *psi0_dev, double *occ,
+                                   pd_lanczos_info *info, hipStream_t stream) {
+    pd_status st = check_basis(b);
+    if (st != PD_OK) return st;
+    if ((st = check_opts(o)) != PD_OK) return st;
+    if (!E0) return fail(PD_EINVAL, "E0 is NULL");
+    if ((st = check_sigma_range(b)) != PD_OK) return st;
+    CoefBlock blk;
+    if ((st = pack_coefficients(b->omega, b->n, eps, V, &blk)) != PD_OK) return st;
+    const size_t need = lanczos_workspace_bytes(b->dim, o);
+    if (need > kStaticScratchBytes)
+        return fail(PD_ERANGE, "workspace of %zu bytes exceeds the static %zu-byte array (use pd_lanczos_ground)",
+                    need, kStaticScratchBytes);
+    if (o->start == PD_START_USER) {
+        if ((st = check_device_ptr(x0_dev, "x0_dev", b->dim * 8)) != PD_OK) return st;
+    }
+    if (psi0_dev) {
+        if ((st = check_device_ptr(psi0_dev, "psi0_dev", b->dim * 8)) != PD_OK) return st;
+    }
+    void *work = nullptr;
+    std::mutex *call_mu = nullptr;
+    if ((st = static_scratch(&work, &call_mu)) != PD_OK) return st;
+    std::lock_guard<std::mutex> lk(*call_mu);
+    st = lanczos_run(b, blk, o, work, kStaticScratchBytes, x0_dev, E0, psi0_dev, occ, info, stream, false);
+    // An early error return may leave work queued: let it finish before the
+    // next call may reuse the array.
+    if (st != PD_OK) (void)hipStreamSynchronize(stream);
+    return st;
 }
 
 size_t pd_lanczos_eigs_workspace_bytes(pd_basis b, int nev, const pd_lanczos_opts *o) {

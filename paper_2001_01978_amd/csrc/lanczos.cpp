@@ -38,6 +38,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "pd_internal.h"
 
@@ -121,9 +122,40 @@ size_t lanczos_workspace_bytes(int64_t dim, const pd_lanczos_opts *o) {
     return layout_for(dim, o->krylov, o->precision).total;
 }
 
+// ---------------------------------------------------------------- static workspace
+// The workspace of pd_lanczos_ground_static: a device array of fixed size in
+// the library's code object, one copy per GPU.  Host code never passes the
+// array's name to a kernel (in host code it only stands in for the symbol):
+// its device address is looked up once per device and kept here.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_static_call_mu[kMaxDevices];
+}  // namespace
+
+pd_status static_scratch(void **ptr, std::mutex **call_mu) {
+    int dev = 0;
+    PD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PD_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PD_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *call_mu = &g_static_call_mu[dev];
+    return PD_OK;
+}
+
 pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_opts *o, void *work,
                       size_t work_bytes, const double *x0, double *E0_out, double *psi0, double *occ_out,
-                      pd_lanczos_info *info_out, hipStream_t s) {
+                      pd_lanczos_info *info_out, hipStream_t s, bool time_products) {
     auto t0 = std::chrono::steady_clock::now();
     const int omega = b->omega, n = b->n;
     const int64_t dim = b->dim;
@@ -245,8 +277,10 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             if (b) (void)hipEventDestroy(b);
         }
     } ev;
-    PD_HIP(hipEventCreate(&ev.a));
-    PD_HIP(hipEventCreate(&ev.b));
+    if (time_products) {
+        PD_HIP(hipEventCreate(&ev.a));
+        PD_HIP(hipEventCreate(&ev.b));
+    }
 
     std::vector<double> alpha(m), beta(m), y(m), yy(m);
     // Column scales: q_j = sc[j] * (stored column j).  Columns are written
@@ -268,7 +302,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             const bool f32_step = y32 && k >= 1;
             // the product of the stored column k (FP32 column for FP32 steps); H q_k = sc[k] * it
             const void *pin = f32_step ? static_cast<const void *>(y32) : static_cast<const void *>(p);
-            PD_HIP(hipEventRecord(ev.a, s));
+            if (time_products) PD_HIP(hipEventRecord(ev.a, s));
             if (f32_step) {
                 PD_HIP(launch_sigma(omega, n, dim, coef, PD_F32, Q32 ? Q32 + (size_t)(k - 1) * ld : x32, y32, s,
                                     dsum64, dsum32, tr));
@@ -276,7 +310,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             } else {
                 PD_HIP(launch_sigma(omega, n, dim, coef, PD_F64, qk, p, s, dsum64, dsum32, tr));
             }
-            PD_HIP(hipEventRecord(ev.b, s));
+            if (time_products) PD_HIP(hipEventRecord(ev.b, s));
             ++info.iterations;
             const double sp = sc[k];
             const double sigma = k > 0 ? alpha[k - 1] : theta;
@@ -310,7 +344,7 @@ pd_status lanczos_run(pd_basis b, const CoefBlock &host_coef, const pd_lanczos_o
             } else {
                 PD_HIP(dev.fetch(kOffC + k, 1));
             }
-            {
+            if (time_products) {
                 float ms = 0.0f;
                 PD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
                 (f32_step ? info.sigma_seconds_f32 : info.sigma_seconds_f64) += 1e-3 * ms;

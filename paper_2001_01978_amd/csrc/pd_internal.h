@@ -245,6 +245,12 @@ int probe_grid(int kind, int64_t n);
 hipError_t launch_stream_probe(int kind, bool nontemporal, const float *a, const float *b, float *c, int64_t n,
                                hipStream_t s);
 
+// lanczos.cpp: the static workspace of pd_lanczos_ground_static.  *ptr: its
+// device address on the current device (looked up once per device);
+// *call_mu: the lock that serialises calls using it on that device.
+constexpr size_t kStaticScratchBytes = PD_STATIC_SCRATCH_BYTES;
+pd_status static_scratch(void **ptr, std::mutex **call_mu);
+
 // tridiag.cpp: lowest eigenpair of the symmetric tridiagonal (alpha, beta).
 int tridiag_lowest(int m, const double *alpha, const double *beta, double *theta, double *y);
 

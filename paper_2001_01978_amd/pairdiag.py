@@ -119,6 +119,8 @@ SIGNATURES = {
     "pd_batched_workspace_bytes": (SZ, [I, P, P, ctypes.POINTER(LanczosOpts)]),
     "pd_lanczos_ground_batched": (I, [I, P, P, P, P, ctypes.POINTER(LanczosOpts), I, P, SZ, P, P,
                                       ctypes.POINTER(LanczosInfo), ctypes.POINTER(BatchInfo), P]),
+    "pd_lanczos_ground_static": (I, [P, P, P, ctypes.POINTER(LanczosOpts), P, ctypes.POINTER(D), P, P,
+                                     ctypes.POINTER(LanczosInfo), P]),
     "pd_stream_probe_bytes": (I64, [I, I64]),
     "pd_stream_probe": (I, [I, P, P, P, I64, P]),
 }
@@ -432,6 +434,36 @@ def lanczos_ground(basis: Basis, eps, V, x0=None, want_psi=True, workspace=None,
                              _dptr(x0) if x0 is not None else None, ctypes.byref(e0),
                              _dptr(psi) if psi is not None else None, _hp(occ), ctypes.byref(info),
                              _stream(stream))
+    _check(st, allow=(PD_ENOCONV,))
+    return GroundState(E0=e0.value, psi=psi, occ=occ, iterations=info.iterations,
+                       iterations_f32=info.iterations_f32, restarts=info.restarts, converged=bool(info.converged),
+                       residual=info.residual, monopole_min=info.monopole_min, seconds=info.seconds,
+                       sigma_seconds_f64=info.sigma_seconds_f64, sigma_seconds_f32=info.sigma_seconds_f32,
+                       fallback_used=bool(info.fallback_used), status=st,
+                       reorth_second_passes=info.reorth_second_passes)
+
+
+STATIC_SCRATCH_BYTES = 256 << 20
+
+
+def lanczos_ground_static(basis: Basis, eps, V, x0=None, want_psi=True, stream=None, **kw) -> GroundState:
+    """Ground state by restarted Lanczos in the library's static workspace
+    (pd_lanczos_ground_static: no workspace argument, no allocation)."""
+    torch = _torch()
+    L = load()
+    if x0 is not None:
+        kw["start"] = "user"
+    o = make_opts(**kw)
+    eps = _host_f64(eps, (basis.omega,))
+    V = _host_f64(V, (basis.omega, basis.omega))
+    psi = torch.empty(basis.dim, dtype=torch.float64, device=basis.device) if want_psi else None
+    occ = np.empty(basis.omega)
+    e0 = ctypes.c_double()
+    info = LanczosInfo()
+    st = L.pd_lanczos_ground_static(basis.handle, _hp(eps), _hp(V), ctypes.byref(o),
+                                    _dptr(x0) if x0 is not None else None, ctypes.byref(e0),
+                                    _dptr(psi) if psi is not None else None, _hp(occ), ctypes.byref(info),
+                                    _stream(stream))
     _check(st, allow=(PD_ENOCONV,))
     return GroundState(E0=e0.value, psi=psi, occ=occ, iterations=info.iterations,
                        iterations_f32=info.iterations_f32, restarts=info.restarts, converged=bool(info.converged),
