@@ -155,7 +155,7 @@ pd_status pd_basis_truncation(pd_basis b, int *truncated, int64_t *full_dim);
  * (PD_F64: double gathers and accumulation; PD_F32: float gathers, float
  * accumulation, coefficients rounded to float).  x and y must not overlap.
  * The handle's device buffer holds 4 coefficient blocks, each with the
- * kernel's per-XCD tile counters.  A call takes a block that is unused, or
+ * kernel's tile counters.  A call takes a block that is unused, or
  * was last used on the same stream (stream order protects it), or whose last
  * product has finished; if every block is busy on other streams, `stream`
  * first waits for the oldest one's product.  So concurrent calls on one

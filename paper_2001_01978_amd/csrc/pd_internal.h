@@ -44,7 +44,7 @@ struct CoefBlock {
     float pad1[15];
     double V64[kMaxOmega * kMaxOmega];
     float V32[kMaxOmega * kMaxOmega];
-    // Tile counters of the sigma kernel: [0, 8) one per XCD, [8] finished
+    // Tile counters of the sigma kernel: [0] the next tile, [8] finished
     // workgroups.  Zero between launches (the last workgroup of a launch
     // clears them), so launches that share a block must be stream-ordered.
     uint32_t sched[16];

@@ -65,7 +65,7 @@ struct Params {
     const T *__restrict__ d;   // omega pair energies
     const T *__restrict__ V;   // omega x omega
     T dsum;                    // sum of d (for the mirrored diagonal)
-    unsigned *sched;           // 9 tile counters, zero on entry and on exit
+    unsigned *sched;           // [0] tile counter, [8] finished workgroups: zero on entry and on exit
 };
 
 // Stages the binomial table C(p, k) * unit (p < omega, k < ks), the couplings and the
@@ -169,7 +169,10 @@ __device__ __forceinline__ void map_gather(const TruncMap<R> &tm, const T *__res
 // most dim * sizeof(T) < 2^32.
 // MAP != 0 (truncated space): row and dim are full-space, x is indexed by
 // truncated rows (tm.self for the diagonal, map_gather for the hops).
-template <typename R, typename T, int NN, bool COMP, bool BUF = false, int MAP = 0>
+// ISSUE_ALL: all NN gathers of a hop block are issued before the first of its
+// multiply-adds (left to itself the compiler interleaves them four at a time,
+// which leaves at most four loads in flight per lane).
+template <typename R, typename T, int NN, bool COMP, bool BUF = false, int MAP = 0, bool ISSUE_ALL = false>
 __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int ks, const R *Ct, const T *Vs,
                                        const T *ds, T dsum, const T *__restrict__ x, R *pre, int pstride,
                                        __amdgpu_buffer_rsrc_t xr, const TruncMap<R> &tm = TruncMap<R>()) {
@@ -261,6 +264,7 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
                 else
                     xv[r] = x[(int64_t)jt];
             }
+            if constexpr (ISSUE_ALL) __builtin_amdgcn_sched_barrier(0);
         } else {
             R jt[NN > 0 ? NN : 1];
 #pragma unroll
@@ -275,8 +279,19 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     return acc;
 }
 
+// With 32-bit ranks, no mirror and at most 17 pairs the product keeps all NN
+// gathers of a hop block in flight (ISSUE_ALL) within 128 VGPRs, so 4 waves
+// per SIMD, the occupancy the LDS allows (measured at 32 and 34 orbits: 6-11%
+// faster in FP64, 7-9% in FP32).  Other instantiations (64-bit ranks, the
+// mirrored space) would spill heavily there and keep the compiler's schedule.
+template <typename R, bool COMP, int NN>
+constexpr bool sigma_issue_all() {
+    return sizeof(R) == 4 && !COMP && NN <= 17;
+}
+
 template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
-__global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
+__global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) void sigma_kernel(Params<R, T> P) {
+    constexpr bool kIssueAll = sigma_issue_all<R, COMP, NN>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int omega = P.omega, ks = P.ks;
     R *Ct;
@@ -287,28 +302,26 @@ __global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
     const __amdgpu_buffer_rsrc_t xr = x_resource<T>(P.x, P.dim);   // used by the BUF gathers only
 
     const int64_t dim = P.dim;
-    if ((gridDim.x & 7) == 0 && P.ntiles >= (int64_t)gridDim.x) {
-        // Workgroups are dealt to the 8 XCDs round-robin (workgroup id mod
-        // 8).  Each XCD owns a contiguous eighth of the tiles and hands them
-        // out in order from its own counter, so the tiles in flight on one
-        // XCD are always the most recently issued ones: a contiguous window
-        // of ranks whose hops share x lines in that XCD's L2.  (A static
-        // stride lets workgroups drift apart over hundreds of tiles and
-        // spreads the window.)
+    if (P.ntiles >= (int64_t)gridDim.x) {
+        // Tiles are handed out in rank order from one counter, so the tiles
+        // in flight at any moment are the most recently issued ones: one
+        // contiguous window of ranks over the whole chip, whose hops gather
+        // from the same regions of x.  (A static stride lets workgroups drift
+        // apart over hundreds of tiles and spreads the window; one counter
+        // per XCD, each over its own eighth of the ranks, keeps eight windows
+        // apart and was measured 7% slower in FP64 at 32 orbits.)
         __shared__ int64_t s_tile;
-        const int xcd = blockIdx.x & 7;
-        const int64_t per_xcd = (P.ntiles + 7) / 8;
-        const int64_t lo = xcd * per_xcd;
-        const int64_t hi = lo + per_xcd < P.ntiles ? lo + per_xcd : P.ntiles;
+        const int64_t hi = P.ntiles;
         for (;;) {
-            if (threadIdx.x == 0) s_tile = lo + (int64_t)atomicAdd(&P.sched[xcd], 1u);
+            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&P.sched[0], 1u);
             __syncthreads();
             const int64_t tile = s_tile;
             __syncthreads();
             if (tile >= hi) break;
             const int64_t row = tile * BLOCK + threadIdx.x;
             if (row < dim)
-                P.y[row] = sigma_row<R, T, NN, COMP, BUF>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK, xr);
+                P.y[row] = sigma_row<R, T, NN, COMP, BUF, 0, kIssueAll>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x,
+                                                                      pre, BLOCK, xr);
         }
         // The last workgroup to finish clears the counters for the next launch.
         if (threadIdx.x == 0) {
@@ -323,7 +336,8 @@ __global__ __launch_bounds__(BLOCK) void sigma_kernel(Params<R, T> P) {
     for (int64_t tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
         const int64_t row = tile * BLOCK + threadIdx.x;
         if (row >= dim) continue;
-        P.y[row] = sigma_row<R, T, NN, COMP, BUF>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre, BLOCK, xr);
+        P.y[row] = sigma_row<R, T, NN, COMP, BUF, 0, kIssueAll>(row, dim, omega, ks, Ct, Vs, ds, P.dsum, P.x, pre,
+                                                              BLOCK, xr);
     }
 }
 
