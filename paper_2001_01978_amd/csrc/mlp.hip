@@ -8,7 +8,8 @@
 //
 // Dense layers run on the matrix cores: operands are rounded from FP32 to
 // BF16 while tiles are staged in LDS, products accumulate in FP32
-// (v_mfma_f32_16x16x16_bf16), and bias / GELU are fused into the store.
+// (gfx950's v_mfma_f32_16x16x32_bf16: 32 products per output per
+// instruction), and bias / GELU are fused into the store.
 #include <cmath>
 
 #include "pd_internal.h"
@@ -16,7 +17,8 @@
 namespace pd {
 namespace mlp {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short to_bf16(float f) {
@@ -38,18 +40,24 @@ __device__ __forceinline__ float gelu_tanh_grad(float x) {
 }
 
 constexpr int kTile = 64;
-constexpr int kK = 16;
+constexpr int kK = 32;            // k per MFMA (16x16x32)
+constexpr int kRow = kK + 8;      // LDS row of a staged tile: 32 BF16 + 16 bytes of padding
 
 // C = op(A) op(B) (M x N, K inner).  op(A)(m, k) = TA ? A[k*lda + m] : A[m*lda + k];
 // op(B)(k, n) = TB ? B[n*ldb + k] : B[k*ldb + n].
 // epilogue 0: C = acc; 1: C = acc + bias[n]; 2: Z = acc + bias[n] stored in C, H = gelu(Z).
+// A 64 x 64 tile per workgroup, four waves of 32 x 32 (2 x 2 MFMA tiles).  Both
+// operands are staged k-contiguous (op(A) as rows m, op(B) transposed as rows
+// n), each thread converting 8 consecutive k of one row and storing them as
+// one 16-byte LDS write, so every MFMA operand is one 16-byte LDS read: lane l
+// takes row (l % 16) of its 16-row slice at k = 8 (l / 16) .. 8 (l / 16) + 7.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const float *__restrict__ A, int lda,
                                                         const float *__restrict__ B, int ldb, float *__restrict__ C,
                                                         int ldc, const float *__restrict__ bias, int epilogue,
                                                         float *__restrict__ H) {
-    __shared__ short As[kTile][kK + 4];
-    __shared__ short Bs[kK][kTile + 4];
+    __shared__ __align__(16) short As[kTile][kRow];
+    __shared__ __align__(16) short Bs[kTile][kRow];   // Bs[n][k] = op(B)(k, n)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -59,42 +67,33 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    const int srow = tid >> 2, sk = (tid & 3) * 8;     // this thread's staging row and k offset
     for (int k0 = 0; k0 < K; k0 += kK) {
-        // stage 64x16 of op(A) and 16x64 of op(B), rounded to BF16, zero outside
+        shortx8 av, bv;
+        const int gm = m0 + srow, gn = n0 + srow;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + q * 256;  // 0..1023
-            const int am = e / kK, ak = e % kK;
-            const int gm = m0 + am, gk = k0 + ak;
-            float av = 0.f;
-            if (gm < M && gk < K) av = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-            As[am][ak] = to_bf16(av);
-            const int bk = e / kTile, bn = e % kTile;
-            const int gk2 = k0 + bk, gn = n0 + bn;
-            float bv = 0.f;
-            if (gk2 < K && gn < N) bv = TB ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
-            Bs[bk][bn] = to_bf16(bv);
+        for (int i = 0; i < 8; ++i) {
+            const int gk = k0 + sk + i;
+            float a = 0.f, b = 0.f;
+            if (gm < M && gk < K) a = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+            if (gn < N && gk < K) b = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+            av[i] = to_bf16(a);
+            bv[i] = to_bf16(b);
         }
+        *reinterpret_cast<shortx8 *>(&As[srow][sk]) = av;
+        *reinterpret_cast<shortx8 *>(&Bs[srow][sk]) = bv;
         __syncthreads();
-        // fragments: lane holds row (lane % 16) of A / column (lane % 16) of B at k = 4*(lane/16) .. +3
-        const int r = lane & 15, kq = (lane >> 4) * 4;
+        const int r = lane & 15, kq = (lane >> 4) * 8;
+        bf16x8 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            bf16x4 a;
-            a[0] = As[wm + i * 16 + r][kq + 0];
-            a[1] = As[wm + i * 16 + r][kq + 1];
-            a[2] = As[wm + i * 16 + r][kq + 2];
-            a[3] = As[wm + i * 16 + r][kq + 3];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                bf16x4 b;
-                b[0] = Bs[kq + 0][wn + j * 16 + r];
-                b[1] = Bs[kq + 1][wn + j * 16 + r];
-                b[2] = Bs[kq + 2][wn + j * 16 + r];
-                b[3] = Bs[kq + 3][wn + j * 16 + r];
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
-            }
+            a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const shortx8 *>(&As[wm + i * 16 + r][kq]));
+            b[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const shortx8 *>(&Bs[wn + i * 16 + r][kq]));
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
     // result: lane holds C[4*(lane/16) + v][lane % 16] of each 16x16 tile

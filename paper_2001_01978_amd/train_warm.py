@@ -3,6 +3,9 @@
     python -m paper_2001_01978_amd.train_warm --omega 24 --n 12 --train 4096 \\
         --out paper_2001_01978_amd/weights/warm_o24_n12.npz --report report.json
 
+Large training sets can be labelled over several runs (--labels-only with
+--train-seed0 and --labels-cache), then joined with --labels-from.
+
 Training instances: the random family at fixed (omega, n) with seeds
 [seed0, seed0 + train); held-out instances: seeds [10^6, 10^6 + heldout).  Labels are the
 half occupations from the batched GPU solver (tol 1e-8).  The report holds
@@ -47,6 +50,10 @@ def main(argv=None):
     ap.add_argument("--train-seed0", type=int, default=0, help="first training seed (training seeds: seed0 .. seed0+train)")
     ap.add_argument("--single", action="store_true",
                     help="label with the single-instance mixed-precision solver (spaces beyond the batched kernel)")
+    ap.add_argument("--labels-only", action="store_true",
+                    help="stop after writing --labels-cache (labels of large training sets over several runs)")
+    ap.add_argument("--labels-from", nargs="*", default=None,
+                    help="npz files of (X, T) to concatenate as the training set instead of solving")
     args = ap.parse_args(argv)
 
     import torch
@@ -60,7 +67,13 @@ def main(argv=None):
         return inputs.family3_instance(seed, omega=om, n=n)
 
     t0 = time.perf_counter()
-    if args.labels_cache and os.path.exists(args.labels_cache):
+    if args.labels_from:
+        parts = [np.load(f, allow_pickle=False) for f in args.labels_from]
+        X = np.concatenate([d["X"] for d in parts])
+        T = np.concatenate([d["T"] for d in parts])
+        log(f"labels from {len(parts)} files: {X.shape}")
+        label_seconds = 0.0
+    elif args.labels_cache and os.path.exists(args.labels_cache):
         d = np.load(args.labels_cache, allow_pickle=False)
         X, T = d["X"], d["T"]
         log(f"labels from {args.labels_cache}: {X.shape}")
@@ -81,6 +94,10 @@ def main(argv=None):
                 np.savez(args.labels_cache, X=np.concatenate(Xs), T=np.concatenate(Ts))
         X, T = np.concatenate(Xs), np.concatenate(Ts)
         label_seconds = time.perf_counter() - t0
+        if args.labels_only:
+            log(f"labels for seeds {args.train_seed0}..{args.train_seed0 + args.train - 1} written to "
+                f"{args.labels_cache} in {label_seconds:.0f} s")
+            return 0
 
     t1 = time.perf_counter()
     net = warm.WarmNet(om, hidden=args.hidden, seed=0)
