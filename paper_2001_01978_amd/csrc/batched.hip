@@ -177,9 +177,9 @@ template <int NN, bool COMP>
 __device__ void wg_sigma_nn(const Instance &I, const Team &T, const Shared &sh, const double *x, double *y) {
     const int ks = I.nn + 2;
     for (int64_t row = T.r0 + threadIdx.x; row < T.r1; row += blockDim.x)
-        y[row] = sigma_detail::sigma_row<uint32_t, double, NN, COMP, false>(row, I.dim, I.omega, ks, sh.Ct, sh.Vs, sh.ds,
-                                                                I.dsum, x, T.pre, (int)blockDim.x,
-                                                                sigma_detail::x_resource<double>(x, I.dim));
+        y[row] = sigma_detail::sigma_row<uint32_t, double, NN, COMP, false, 0, true>(
+            row, I.dim, I.omega, ks, sh.Ct, sh.Vs, sh.ds, I.dsum, x, T.pre, (int)blockDim.x,
+            sigma_detail::x_resource<double>(x, I.dim));
 }
 
 // Instances arrive with n <= omega - n (the host maps the others to their
