@@ -417,6 +417,13 @@ def main():
         import traceback
         traceback.print_exc()
         OUT["error"] = f"{type(e).__name__}: {e}"
+    if OUT.get("value"):
+        # Context only (another machine, another workload): the paper's CPU rate, 6.469e-8 CPU-seconds
+        # per off-diagonal non-zero on an i7-7700K (Sec. 5.3), about 1.2e8 non-zeros/s of wall time on
+        # its 8 threads.
+        OUT["paper_context"] = {"nnz_per_s_wall_8_threads": 1.2e8, "nnz_per_cpu_second": 1.0 / 6.469e-8,
+                                "hardware": "Intel i7-7700K, 8 threads, FP64",
+                                "value_over_paper_wall_rate": OUT["value"] / 1.2e8}
     OUT["bench_seconds"] = time.perf_counter() - T_START
     emit()
 

@@ -149,3 +149,15 @@ def test_new_entry_points_reject_bad_arguments_before_device_work():
     so = pdg.ScfOpts(max_iter=10, tol=1e-8, mixing=0.5, reuse_psi=1)
     assert L.pd_scf_ground(None, pdg._hp(eps), pdg._hp(V), pdg._hp(V), ctypes.byref(so), ctypes.byref(o), None, 0,
                            None, None, ctypes.byref(E), None, None, None) == pdg.PD_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it says so and exits 2
+    before touching a GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
