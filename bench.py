@@ -462,7 +462,9 @@ def run(args, torch, np, inputs, pairdiag, om, n, eps, V, K, D):
                 "kernel": kernel, "avg_launch_ms": avg * 1e3, "launches_timed": args.steps,
                 "achieved_is": "HBM bytes per launch (rocprofv3 FETCH_SIZE x copy-calibrated read scale + "
                                "WRITE_SIZE, profiles/" + COUNTERS.format(om=om, n=n) + ".txt) / mean HIP-event "
-                               "launch time in this run",
+                               "launch time in this run; FETCH_SIZE counts every byte the L2s fetch from below "
+                               "them, hits in the 256 MB Infinity Cache included, so it bounds true HBM traffic "
+                               "from above",
                 "achievable_GBps": achievable, "frac_of_achievable": ach / achievable if ach else None,
                 "probes_GBps": probes,
                 "algorithmic": {"gather_model_bytes": balg, "gather_model_GBps": balg / avg / 1e9,
