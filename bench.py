@@ -397,7 +397,8 @@ def main():
         torch.cuda.empty_cache()
         basis = pairdiag.Basis(om, n, store_states=False)
         for dt in (torch.float32, torch.float64):
-            timed_products(torch, basis, eps, V, dt, args.sigma_reps, 0, 7)
+            _, launches = timed_products(torch, basis, eps, V, dt, args.sigma_reps, 0, 7)
+            log(f"{dt}: mean launch {1e3 * sum(launches) / len(launches):.3f} ms over {len(launches)}")
         log(f"kernel-only run done (kernel source {kernel_source_hash()})")
         return
 

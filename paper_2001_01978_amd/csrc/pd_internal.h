@@ -44,11 +44,14 @@ struct CoefBlock {
     float pad1[15];
     double V64[kMaxOmega * kMaxOmega];
     float V32[kMaxOmega * kMaxOmega];
-    // Tile counters of the sigma kernel: [0] the next tile, [8] finished
-    // workgroups.  Zero between launches (the last workgroup of a launch
-    // clears them), so launches that share a block must be stream-ordered.
-    uint32_t sched[16];
+    // Tile counters of the sigma kernel: [0] the next tile (or chunk of
+    // tiles), [8] finished workgroups, [16..31] one 64-bit word per XCD (its
+    // current chunk and the tiles taken from it).  Zero between launches (the
+    // last workgroup of a launch clears them), so launches that share a block
+    // must be stream-ordered.
+    uint32_t sched[32];
 };
+static_assert(offsetof(CoefBlock, sched) % 8 == 0, "the per-XCD words take 64-bit atomics");
 constexpr size_t kCoefBytes = (sizeof(CoefBlock) + 255) & ~size_t(255);
 
 // A basis handle carries kSigmaSlots coefficient blocks for pd_sigma, so

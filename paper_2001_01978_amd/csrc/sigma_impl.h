@@ -65,7 +65,8 @@ struct Params {
     const T *__restrict__ d;   // omega pair energies
     const T *__restrict__ V;   // omega x omega
     T dsum;                    // sum of d (for the mirrored diagonal)
-    unsigned *sched;           // [0] tile counter, [8] finished workgroups: zero on entry and on exit
+    unsigned *sched;           // CoefBlock::sched: zero on entry and on exit
+    int chunk;                 // tiles per XCD chunk (FP64 products)
 };
 
 // Stages the binomial table C(p, k) * unit (p < omega, k < ks), the couplings and the
@@ -289,6 +290,13 @@ constexpr bool sigma_issue_all() {
     return sizeof(R) == 4 && !COMP && NN <= 17;
 }
 
+// FP64 products take tiles in per-XCD chunks (see the scheduler in sigma_kernel).
+template <typename T>
+constexpr bool sigma_xcd_chunks() {
+    return sizeof(T) == 8;
+}
+constexpr int kMaxXcdChunk = 128;
+
 template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
 __global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) void sigma_kernel(Params<R, T> P) {
     constexpr bool kIssueAll = sigma_issue_all<R, COMP, NN>();
@@ -303,17 +311,49 @@ __global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) vo
 
     const int64_t dim = P.dim;
     if (P.ntiles >= (int64_t)gridDim.x) {
-        // Tiles are handed out in rank order from one counter, so the tiles
-        // in flight at any moment are the most recently issued ones: one
-        // contiguous window of ranks over the whole chip, whose hops gather
-        // from the same regions of x.  (A static stride lets workgroups drift
-        // apart over hundreds of tiles and spreads the window; one counter
-        // per XCD, each over its own eighth of the ranks, keeps eight windows
-        // apart and was measured 7% slower in FP64 at 32 orbits.)
+        // Tiles are handed out in rank order, so the tiles in flight at any
+        // moment are the most recently issued ones: one contiguous window of
+        // ranks over the whole chip, whose hops gather from the same regions
+        // of x (a static stride lets workgroups drift apart over hundreds of
+        // tiles and spreads the window; one counter per XCD, each over its own
+        // eighth of the ranks, keeps eight windows apart, and their targets
+        // overflow the Infinity Cache: measured 7% slower in FP64).
+        // FP64: the global counter hands out chunks of P.chunk tiles, each to
+        // one XCD (workgroup id mod 8 is the XCD), whose workgroups take its
+        // tiles in order.  The eight XCDs still share one window, and each
+        // XCD's L2 sees contiguous runs of rows, whose nearby hops it then
+        // serves itself (4% faster in FP64 at 32 and 34 orbits; FP32 gains
+        // nothing and keeps one tile per request).
         __shared__ int64_t s_tile;
         const int64_t hi = P.ntiles;
+        unsigned long long *xw = reinterpret_cast<unsigned long long *>(P.sched + 16);
         for (;;) {
-            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&P.sched[0], 1u);
+            if (threadIdx.x == 0) {
+                if constexpr (sigma_xcd_chunks<T>()) {
+                    // xw[xcd] = (global chunk + 1) << 32 | tiles taken from it.
+                    // Whoever takes the tile one past its end (or the very
+                    // first request) fetches the next chunk and installs it;
+                    // requests that arrive meanwhile ask again.
+                    const int S = P.chunk;
+                    unsigned long long *w = xw + (blockIdx.x & 7);
+                    for (;;) {
+                        const unsigned long long v = atomicAdd(w, 1ull);
+                        const unsigned c = (unsigned)(v >> 32), o = (unsigned)v;
+                        if (c != 0 && o < (unsigned)S) {
+                            s_tile = (int64_t)(c - 1) * S + o;
+                            break;
+                        }
+                        if (c == 0 ? o == 0 : o == (unsigned)S) {
+                            const unsigned g = atomicAdd(&P.sched[0], 1u);
+                            atomicExch(w, ((unsigned long long)(g + 1) << 32) | 1ull);
+                            s_tile = (int64_t)g * S;
+                            break;
+                        }
+                    }
+                } else {
+                    s_tile = (int64_t)atomicAdd(&P.sched[0], 1u);
+                }
+            }
             __syncthreads();
             const int64_t tile = s_tile;
             __syncthreads();
@@ -327,7 +367,10 @@ __global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) vo
         if (threadIdx.x == 0) {
             __threadfence();
             if (atomicAdd(&P.sched[8], 1u) == gridDim.x - 1) {
-                for (int i = 0; i < 9; ++i) atomicExch(&P.sched[i], 0u);
+                atomicExch(&P.sched[0], 0u);
+                if constexpr (sigma_xcd_chunks<T>())
+                    for (int i = 0; i < 8; ++i) atomicExch(&xw[i], 0ull);
+                atomicExch(&P.sched[8], 0u);
                 __threadfence();
             }
         }
@@ -364,6 +407,9 @@ hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
     P.ntiles = (P.dim + BLOCK - 1) / BLOCK;
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
     if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
+    // Chunks of up to 128 tiles, at least two per workgroup of the grid, so
+    // that small spaces still spread over all eight XCDs.
+    P.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxXcdChunk, P.ntiles / (2 * grid)));
     hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP, BLOCK, BUF>), dim3((unsigned)grid), dim3(BLOCK), smem, stream,
                        P);
     return hipGetLastError();
@@ -487,6 +533,7 @@ hipError_t launch_trunc_typed(int omega, int n, const TruncSpace &tr, const T *d
     Q.P.V = V;
     Q.P.dsum = dsum;
     Q.P.sched = nullptr;
+    Q.P.chunk = 1;
     Q.kranks = static_cast<const R *>(tr.kranks);
     Q.words = tr.words;
     Q.kept = tr.kept;
@@ -511,6 +558,7 @@ hipError_t launch_typed(int omega, int n, int64_t dim, const T *d, const T *V, T
     P.V = V;
     P.dsum = dsum;
     P.sched = sched;
+    P.chunk = 1;
     return comp ? dispatch_nn<R, T, true>(P, stream) : dispatch_nn<R, T, false>(P, stream);
 }
 
