@@ -66,7 +66,7 @@ struct Params {
     const T *__restrict__ V;   // omega x omega
     T dsum;                    // sum of d (for the mirrored diagonal)
     unsigned *sched;           // CoefBlock::sched: zero on entry and on exit
-    int chunk;                 // tiles per XCD chunk (FP64 products)
+    int chunk;                 // tiles per XCD chunk (FP64 products on large spaces), 0: one tile per request
 };
 
 // Stages the binomial table C(p, k) * unit (p < omega, k < ks), the couplings and the
@@ -296,6 +296,7 @@ constexpr bool sigma_xcd_chunks() {
     return sizeof(T) == 8;
 }
 constexpr int kMaxXcdChunk = 128;
+constexpr int kMinXcdChunk = 16;
 
 template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
 __global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) void sigma_kernel(Params<R, T> P) {
@@ -318,18 +319,22 @@ __global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) vo
         // tiles and spreads the window; one counter per XCD, each over its own
         // eighth of the ranks, keeps eight windows apart, and their targets
         // overflow the Infinity Cache: measured 7% slower in FP64).
-        // FP64: the global counter hands out chunks of P.chunk tiles, each to
-        // one XCD (workgroup id mod 8 is the XCD), whose workgroups take its
-        // tiles in order.  The eight XCDs still share one window, and each
-        // XCD's L2 sees contiguous runs of rows, whose nearby hops it then
-        // serves itself (4% faster in FP64 at 32 and 34 orbits; FP32 gains
-        // nothing and keeps one tile per request).
+        // FP64 on large spaces (P.chunk > 0): the global counter hands out
+        // chunks of P.chunk tiles, each to one XCD (workgroup id mod 8 is the
+        // XCD), whose workgroups take its tiles in order.  The eight XCDs
+        // still share one window, and each XCD's L2 sees contiguous runs of
+        // rows, whose nearby hops it then serves itself (4% faster in FP64 at
+        // 32 and 34 orbits; FP32 gains nothing and keeps one tile per
+        // request).  Small spaces keep one tile per request too: with short
+        // chunks the refills come so often that the workgroups waiting on
+        // them dominate (chunks of one tile made a 2.7e6-state product 20x
+        // slower).
         __shared__ int64_t s_tile;
         const int64_t hi = P.ntiles;
         unsigned long long *xw = reinterpret_cast<unsigned long long *>(P.sched + 16);
         for (;;) {
             if (threadIdx.x == 0) {
-                if constexpr (sigma_xcd_chunks<T>()) {
+                if (sigma_xcd_chunks<T>() && P.chunk > 0) {
                     // xw[xcd] = (global chunk + 1) << 32 | tiles taken from it.
                     // Whoever takes the tile one past its end (or the very
                     // first request) fetches the next chunk and installs it;
@@ -407,9 +412,13 @@ hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
     P.ntiles = (P.dim + BLOCK - 1) / BLOCK;
     int64_t grid = P.ntiles < kMaxGrid ? P.ntiles : kMaxGrid;
     if (grid >= 64) grid &= ~int64_t(7);  // a multiple of the XCD count
-    // Chunks of up to 128 tiles, at least two per workgroup of the grid, so
-    // that small spaces still spread over all eight XCDs.
-    P.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxXcdChunk, P.ntiles / (2 * grid)));
+    // Chunks of up to 128 tiles, at least two per workgroup of the grid;
+    // below 16 tiles a chunk (spaces under about 6.7e7 states with 512-row
+    // tiles) every request takes one tile from the global counter.
+    {
+        const int64_t s = std::min<int64_t>(kMaxXcdChunk, P.ntiles / (2 * grid));
+        P.chunk = s >= kMinXcdChunk ? (int)s : 0;
+    }
     hipLaunchKernelGGL((sigma_kernel<R, T, NN, COMP, BLOCK, BUF>), dim3((unsigned)grid), dim3(BLOCK), smem, stream,
                        P);
     return hipGetLastError();
@@ -533,7 +542,7 @@ hipError_t launch_trunc_typed(int omega, int n, const TruncSpace &tr, const T *d
     Q.P.V = V;
     Q.P.dsum = dsum;
     Q.P.sched = nullptr;
-    Q.P.chunk = 1;
+    Q.P.chunk = 0;
     Q.kranks = static_cast<const R *>(tr.kranks);
     Q.words = tr.words;
     Q.kept = tr.kept;
@@ -558,7 +567,7 @@ hipError_t launch_typed(int omega, int n, int64_t dim, const T *d, const T *V, T
     P.V = V;
     P.dsum = dsum;
     P.sched = sched;
-    P.chunk = 1;
+    P.chunk = 0;
     return comp ? dispatch_nn<R, T, true>(P, stream) : dispatch_nn<R, T, false>(P, stream);
 }
 
