@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--kernel-only", action="store_true",
                     help="for counter runs: the library's 1 GiB copy kernel (the known-size reference), then "
                          "--sigma-reps FP32 and FP64 products of the workload, and exit")
+    ap.add_argument("--trunc", action="store_true",
+                    help="with --kernel-only: the truncated-space products (the space cut to 1e8 states, 1e8 "
+                         "histogram bins, bitmap map) instead of the full ones")
     ap.add_argument("--sigma-reps", type=int, default=2)
     return ap.parse_args()
 
@@ -395,7 +398,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
-        basis = pairdiag.Basis(om, n, store_states=False)
+        if args.trunc:
+            basis = pairdiag.Basis.truncated(om, n, eps, V, 100_000_000, 10**8)
+            log(f"truncated space: {basis.dim} kept states")
+        else:
+            basis = pairdiag.Basis(om, n, store_states=False)
         for dt in (torch.float32, torch.float64):
             _, launches = timed_products(torch, basis, eps, V, dt, args.sigma_reps, 0, 7)
             log(f"{dt}: mean launch {1e3 * sum(launches) / len(launches):.3f} ms over {len(launches)}")
