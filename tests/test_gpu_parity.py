@@ -127,8 +127,9 @@ def test_sigma_random_f64_and_f32(torch_cuda, pdg, oracle_mod, om, n):
 
 
 def test_sigma_repeated_launches_cover_every_row(torch_cuda, pdg, oracle_mod):
-    """Omega=24, n=12 (10,563 tiles: the per-XCD tile counters are used): every
-    launch writes every row, whatever ran before on the same basis."""
+    """Omega=24, n=12 (5,282 tiles of 512 rows, more than the grid's
+    workgroups: tiles come from the tile counter): every launch writes every
+    row, whatever ran before on the same basis."""
     torch = torch_cuda
     om, n, eps, V = inputs.dyadic_instance(24, 12, seed=77)
     d = math.comb(om, n)
@@ -194,7 +195,8 @@ def test_sigma_full_size_omega28_sampled_f64(torch_cuda, pdg, oracle_mod):
 def test_sigma_full_size_dyadic_exact_sampled(torch_cuda, pdg, oracle_mod, om, n):
     """FP64 and FP32 at Omega=28 (4.0e7 states), Omega=32 (6.0e8 states, the
     benchmark's space and launch) and Omega=34 (2.3e9 states; FP64 there runs
-    256-thread workgroups): exact."""
+    256-thread workgroups): exact on sampled rows, and every row written (the
+    FP64 launches at 32 and 34 orbits hand out tiles in per-XCD chunks)."""
     torch = torch_cuda
     _, _, eps, V = inputs.dyadic_instance(om, n, 5)
     d = math.comb(om, n)
@@ -202,13 +204,58 @@ def test_sigma_full_size_dyadic_exact_sampled(torch_cuda, pdg, oracle_mod, om, n
     dts = (torch.float64, torch.float32)
     for dt in dts:
         x = torch.randint(-63, 64, (d,), dtype=dt, device="cuda")
-        y = b.sigma(eps, V, x)
+        y = torch.full_like(x, float("nan"))
+        b.sigma(eps, V, x, y)
+        assert not bool(torch.isnan(y).any()), (dt, "a row was not written")
         rows = _sampled_rows(d, 4000, 2)
         want, _ = _oracle_rows_on_device_x(oracle_mod, om, n, eps, V, x, rows)
         got = y[torch.tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
         assert np.array_equal(got, want), dt
         del x, y
         torch.cuda.empty_cache()
+
+
+def test_sigma_chunked_schedule_every_row(torch_cuda, pdg, oracle_mod):
+    """Omega=30, n=15 (1.55e8 states, 302,964 tiles: FP64 tiles go out in
+    per-XCD chunks of 36): launches in a row, FP32 launches (one tile per
+    request) between them, and two streams sharing the handle; every launch
+    writes every row, all launches agree bit for bit, and sampled rows equal
+    the oracle exactly."""
+    torch = torch_cuda
+    om, n, eps, V = inputs.dyadic_instance(30, 15, 11)
+    d = math.comb(om, n)
+    b = pdg.Basis(om, n, store_states=False)
+    x = torch.randint(-63, 64, (d,), dtype=torch.float64, device="cuda")
+    x32 = x.float()
+    ref = None
+    for dt in (torch.float64, torch.float32, torch.float64, torch.float64):
+        xi = x if dt == torch.float64 else x32
+        y = torch.full_like(xi, float("nan"))
+        b.sigma(eps, V, xi, y)
+        assert not bool(torch.isnan(y).any()), (dt, "a row was not written")
+        if ref is None:
+            ref = y
+        else:
+            assert torch.equal(y.double(), ref), dt
+        del y
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    ys = []
+    for k in range(4):
+        st = streams[k % 2]
+        with torch.cuda.stream(st):
+            y = torch.full_like(x, float("nan"))
+            b.sigma(eps, V, x, y, stream=st)
+            ys.append(y)
+    torch.cuda.synchronize()
+    for y in ys:
+        assert torch.equal(y, ref)
+    rows = _sampled_rows(d, 2000, 4)
+    want, _ = _oracle_rows_on_device_x(oracle_mod, om, n, eps, V, x, rows)
+    got = ref[torch.tensor(rows, device="cuda")].cpu().numpy()
+    assert np.array_equal(got, want)
+    del x, x32, ys, ref
+    torch.cuda.empty_cache()
 
 
 def test_sigma_rank64_path_sampled(torch_cuda, pdg, oracle_mod):

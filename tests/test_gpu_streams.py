@@ -39,8 +39,8 @@ def _case(oracle_mod, om, n, seed):
 
 
 def test_sigma_two_streams_one_handle(torch_cuda, pdg, oracle_mod):
-    """Omega=24, n=12 (2.7e6 states, 5282 tiles per product through the
-    per-XCD tile counters): products issued alternately on two streams with
+    """Omega=24, n=12 (2.7e6 states, 5282 tiles per product from the tile
+    counter): products issued alternately on two streams with
     two different coefficient sets, nothing synchronised between them, more
     products in flight than the handle has coefficient blocks."""
     torch = torch_cuda
