@@ -98,6 +98,8 @@ def parse():
 
 KERNEL_SOURCES = ["paper_2001_01978_amd/csrc/sigma_impl.h"]
 COUNTERS = "sigma_omega{om}_n{n}_counters"
+PIPELINE = "sigma_omega{om}_n{n}_pipeline_counters"
+CLOCK_HZ, N_CU, N_SIMD = 2.4e9, 256, 1024
 
 
 def kernel_source_hash():
@@ -459,6 +461,23 @@ def run(args, torch, np, inputs, pairdiag, om, n, eps, V, K, D):
     achievable = max(probes.values())
     log("stream probes: " + ", ".join(f"{k} {v:.0f}" for k, v in probes.items()) + " GB/s")
 
+    pipe = counters_from_profiles(PIPELINE.format(om=om, n=n))
+
+    def pipeline(avg, tag):
+        # Busy fractions of the units that bound the product, from the per-launch SQ/TA/L1 counter totals
+        # of the committed pipeline profile over this run's launch time (2.4 GHz; 256 texture addressers;
+        # 1024 SIMDs, 4 cycles per wave64 VALU instruction).
+        if not pipe or f"ta_busy_cycles_per_launch_{tag}" not in pipe:
+            return None
+        cyc = avg * CLOCK_HZ
+        ta = float(pipe[f"ta_busy_cycles_per_launch_{tag}"])
+        valu = float(pipe[f"valu_instructions_per_launch_{tag}"])
+        vmem = float(pipe[f"vmem_read_instructions_per_launch_{tag}"])
+        l1 = float(pipe[f"l1_accesses_per_launch_{tag}"])
+        return {"ta_busy": ta / (N_CU * cyc), "valu_busy": valu * 4 / (N_SIMD * cyc),
+                "ta_cycles_per_gather": ta / vmem, "l1_accesses_per_gather": l1 / vmem,
+                "source": "profiles/" + PIPELINE.format(om=om, n=n) + ".txt"}
+
     def roof(avg, es, key_bytes, kernel):
         cnt = counters_from_profiles(COUNTERS.format(om=om, n=n))
         dram = float(cnt[key_bytes]) if cnt and key_bytes in cnt else None
@@ -479,13 +498,17 @@ def run(args, torch, np, inputs, pairdiag, om, n, eps, V, K, D):
                                 "compulsory_bytes": bmin, "compulsory_GBps": bmin / avg / 1e9,
                                 "hbm_over_compulsory": dram / bmin if dram else None,
                                 "hbm_over_gather_model": dram / balg if dram else None},
-                "valu": {"ops_per_nonzero": OPS_PER_NONZERO, "achieved_Tops": D * K * OPS_PER_NONZERO / avg / 1e12,
+                "valu": {"kind": "algorithmic: the lane operations per non-zero the method needs (hand count); "
+                                 "pipeline.valu_busy is the measured issue",
+                         "ops_per_nonzero": OPS_PER_NONZERO, "achieved_Tops": D * K * OPS_PER_NONZERO / avg / 1e12,
                          "peak_Tops": PEAK_VALU_TOPS,
                          "frac": D * K * OPS_PER_NONZERO / avg / 1e12 / PEAK_VALU_TOPS},
                 "nnz_per_s": D * K / avg}
 
     OUT["roofline"] = roof(avg64, 8, "hbm_bytes_per_launch_f64", "sigma_kernel<uint32,double,16> (FP64 product)")
+    OUT["roofline"]["pipeline"] = pipeline(avg64, "f64")
     OUT["roofline_f32"] = roof(avg32, 4, "hbm_bytes_per_launch_f32", "sigma_kernel<uint32,float,16> (FP32 product)")
+    OUT["roofline_f32"]["pipeline"] = pipeline(avg32, "f32")
 
     # ---- time-to-E0: plain FP64, mixed, warm (once each)
     kf64 = args.krylov_f64 or args.krylov
