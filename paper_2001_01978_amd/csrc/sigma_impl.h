@@ -51,6 +51,9 @@ namespace sigma_detail {
 
 constexpr int kThreads = 512;           // default workgroup size (and per-lane slot stride)
 constexpr size_t kLdsPerCU = 160 * 1024;
+// Dynamic LDS a workgroup may take: the CU's 160 KB less room for the
+// kernels' static LDS (the tile index).
+constexpr size_t kLdsUsable = kLdsPerCU - 1024;
 constexpr int64_t kMaxGrid = 256 * 16;
 
 template <typename R, typename T>
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) vo
 template <typename R, typename T, int NN, int BLOCK>
 constexpr size_t lds_limit() {
     const size_t need = ((table_bytes<R, T>(kMaxOmega, NN + 2) + 15) & ~size_t(15)) + prefix_bytes<R>(NN, BLOCK);
-    return need < kLdsPerCU - 1024 ? need : kLdsPerCU - 1024;
+    return need < kLdsUsable ? need : kLdsUsable;
 }
 
 template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
@@ -431,7 +434,7 @@ template <typename R, typename T, int NN, bool COMP>
 hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
     const size_t tables = (table_bytes<R, T>(P.omega, P.ks) + 15) & ~size_t(15);
     const size_t s512 = tables + prefix_bytes<R>(NN, 512), s256 = tables + prefix_bytes<R>(NN, 256);
-    const size_t waves512 = (kLdsPerCU / s512) * 8, waves256 = std::min<size_t>((kLdsPerCU / s256) * 4, 16);
+    const size_t waves512 = (kLdsUsable / s512) * 8, waves256 = std::min<size_t>((kLdsUsable / s256) * 4, 16);
     // Byte-offset buffer gathers (FP32, every byte offset of x within 32 bits;
     // measured slower than 64-bit global loads for FP64 gathers).
     constexpr bool kCanBuf = sizeof(R) == 4 && sizeof(T) == 4;

@@ -258,18 +258,29 @@ def test_sigma_chunked_schedule_every_row(torch_cuda, pdg, oracle_mod):
     torch.cuda.empty_cache()
 
 
-def test_sigma_rank64_path_sampled(torch_cuda, pdg, oracle_mod):
-    """dim = C(35,17) = 4.5e9 > 2^32: 64-bit rank arithmetic, FP32 vectors (18 GB each)."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sigma_rank64_path_sampled(torch_cuda, pdg, oracle_mod, dtype):
+    """dim = C(35,17) = 4.5e9 > 2^32: 64-bit rank arithmetic; FP32 (18 GB
+    vectors) and FP64 (36 GB vectors, where 512-thread workgroups would need
+    all but 1 KB of a CU's LDS and 256-thread ones are taken): exact on
+    sampled rows, every row written."""
+    import gc
     torch = torch_cuda
+    gc.collect()
+    torch.cuda.empty_cache()
     om, n, eps, V = inputs.dyadic_instance(35, 17, 8)
     d = math.comb(om, n)
     assert d > 2 ** 32
     b = pdg.Basis(om, n, store_states=False)
-    x = torch.randint(-63, 64, (d,), dtype=torch.float32, device="cuda")
-    y = b.sigma(eps, V, x)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    x = torch.randint(-63, 64, (d,), dtype=tdt, device="cuda")
+    y = torch.full_like(x, float("nan"))
+    b.sigma(eps, V, x, y)
+    written = not bool(torch.isnan(y).any())
     rows = _sampled_rows(d, 1500, 3)
     want, _ = _oracle_rows_on_device_x(oracle_mod, om, n, eps, V, x, rows)
     got = y[torch.tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
     del x, y
     torch.cuda.empty_cache()
+    assert written, "a row was not written"
     assert np.array_equal(got, want)
