@@ -283,14 +283,17 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     return acc;
 }
 
-// With 32-bit ranks, no mirror and at most 17 pairs the product keeps all NN
-// gathers of a hop block in flight (ISSUE_ALL) within 128 VGPRs, so 4 waves
-// per SIMD, the occupancy the LDS allows (measured at 32 and 34 orbits: 6-11%
-// faster in FP64, 7-9% in FP32).  Other instantiations (64-bit ranks, the
-// mirrored space) would spill heavily there and keep the compiler's schedule.
+// With 32-bit ranks and at most 17 pairs the product keeps all NN gathers of
+// a hop block in flight (ISSUE_ALL) within 128 VGPRs, so 4 waves per SIMD,
+// the occupancy the LDS allows (measured at 32 and 34 orbits: 6-11% faster in
+// FP64, 7-9% in FP32).  The mirrored space's FP64 kernel at 16 pairs spills
+// 16-24 bytes per lane there and is still faster (32 orbits, 17 pairs: 91.6
+// -> 79.8 ms; 34 orbits, 18 pairs: 515 -> 363 ms); a mirrored space with 17
+// pairs has at least C(35, 17) > 2^32 states, so 64-bit ranks.  With 64-bit
+// ranks the kernels would spill heavily and keep the compiler's schedule.
 template <typename R, bool COMP, int NN>
 constexpr bool sigma_issue_all() {
-    return sizeof(R) == 4 && !COMP && NN <= 17;
+    return sizeof(R) == 4 && NN <= 17;
 }
 
 // FP64 products take tiles in per-XCD chunks (see the scheduler in sigma_kernel).

@@ -258,6 +258,34 @@ def test_sigma_chunked_schedule_every_row(torch_cuda, pdg, oracle_mod):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("om,n,dtype", [(32, 17, "f64"), (32, 17, "f32"), (35, 18, "f32")])
+def test_sigma_mirrored_full_size_sampled(torch_cuda, pdg, oracle_mod, om, n, dtype):
+    """n > Omega/2 at full size: the mirrored kernel (holes as particles,
+    ranks dim-1-k) on 5.65e8 states (32 orbits, 17 pairs; FP64 takes the
+    per-XCD chunk schedule) and on 4.5e9 states (35 orbits, 18 pairs, 64-bit
+    ranks): exact on sampled rows, every row written."""
+    import gc
+    torch = torch_cuda
+    gc.collect()
+    torch.cuda.empty_cache()
+    _, _, eps, V = inputs.dyadic_instance(om, n, 9)
+    d = math.comb(om, n)
+    assert n > om - n
+    b = pdg.Basis(om, n, store_states=False)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    x = torch.randint(-63, 64, (d,), dtype=tdt, device="cuda")
+    y = torch.full_like(x, float("nan"))
+    b.sigma(eps, V, x, y)
+    written = not bool(torch.isnan(y).any())
+    rows = _sampled_rows(d, 1500, 6)
+    want, _ = _oracle_rows_on_device_x(oracle_mod, om, n, eps, V, x, rows)
+    got = y[torch.tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
+    del x, y
+    torch.cuda.empty_cache()
+    assert written, "a row was not written"
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_sigma_rank64_path_sampled(torch_cuda, pdg, oracle_mod, dtype):
     """dim = C(35,17) = 4.5e9 > 2^32: 64-bit rank arithmetic; FP32 (18 GB
