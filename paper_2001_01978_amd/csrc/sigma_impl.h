@@ -283,17 +283,22 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
     return acc;
 }
 
-// With 32-bit ranks and at most 17 pairs the product keeps all NN gathers of
-// a hop block in flight (ISSUE_ALL) within 128 VGPRs, so 4 waves per SIMD,
+// With at most 17 pairs the product keeps all NN gathers of a hop block in
+// flight (ISSUE_ALL).  32-bit ranks: within 128 VGPRs, so 4 waves per SIMD,
 // the occupancy the LDS allows (measured at 32 and 34 orbits: 6-11% faster in
-// FP64, 7-9% in FP32).  The mirrored space's FP64 kernel at 16 pairs spills
+// FP64, 7-9% in FP32); the mirrored space's FP64 kernel at 16 pairs spills
 // 16-24 bytes per lane there and is still faster (32 orbits, 17 pairs: 91.6
-// -> 79.8 ms; 34 orbits, 18 pairs: 515 -> 363 ms); a mirrored space with 17
-// pairs has at least C(35, 17) > 2^32 states, so 64-bit ranks.  With 64-bit
-// ranks the kernels would spill heavily and keep the compiler's schedule.
+// -> 79.8 ms; 34 orbits, 18 pairs: 515 -> 363 ms).  64-bit ranks: 3 waves
+// per SIMD, without spills when not mirrored (35 orbits, 17 pairs: 1557 ->
+// 1348 ms FP64, 803 -> 700 ms FP32); mirrored they spill up to 188 bytes per
+// lane and ran 2.3-3.2x slower, so they keep the compiler's schedule.
 template <typename R, bool COMP, int NN>
 constexpr bool sigma_issue_all() {
-    return sizeof(R) == 4 && NN <= 17;
+    return NN <= 17 && (sizeof(R) == 4 || !COMP);
+}
+template <typename R, bool COMP, int NN>
+constexpr int sigma_min_waves() {
+    return sigma_issue_all<R, COMP, NN>() ? (sizeof(R) == 4 ? 4 : 3) : 1;
 }
 
 // FP64 products take tiles in per-XCD chunks (see the scheduler in sigma_kernel).
@@ -305,7 +310,7 @@ constexpr int kMaxXcdChunk = 128;
 constexpr int kMinXcdChunk = 16;
 
 template <typename R, typename T, int NN, bool COMP, int BLOCK, bool BUF>
-__global__ __launch_bounds__(BLOCK, (sigma_issue_all<R, COMP, NN>() ? 4 : 1)) void sigma_kernel(Params<R, T> P) {
+__global__ __launch_bounds__(BLOCK, (sigma_min_waves<R, COMP, NN>())) void sigma_kernel(Params<R, T> P) {
     constexpr bool kIssueAll = sigma_issue_all<R, COMP, NN>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int omega = P.omega, ks = P.ks;
