@@ -258,6 +258,30 @@ def test_sigma_chunked_schedule_every_row(torch_cuda, pdg, oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_sigma_most_pairs_that_fit(torch_cuda, pdg, oracle_mod):
+    """Omega=36, n=18: 9.1e9 states, 18 pairs (the most whose vectors fit the
+    device: 19 pairs need at least C(38, 19) = 3.5e10 states), 64-bit ranks,
+    FP32 vectors of 36 GB: exact on sampled rows, every row written."""
+    import gc
+    torch = torch_cuda
+    gc.collect()
+    torch.cuda.empty_cache()
+    om, n, eps, V = inputs.dyadic_instance(36, 18, 12)
+    d = math.comb(om, n)
+    b = pdg.Basis(om, n, store_states=False)
+    x = torch.randint(-63, 64, (d,), dtype=torch.float32, device="cuda")
+    y = torch.full_like(x, float("nan"))
+    b.sigma(eps, V, x, y)
+    written = not bool(torch.isnan(y).any())
+    rows = _sampled_rows(d, 800, 7)
+    want, _ = _oracle_rows_on_device_x(oracle_mod, om, n, eps, V, x, rows)
+    got = y[torch.tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
+    del x, y
+    torch.cuda.empty_cache()
+    assert written, "a row was not written"
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("om,n,dtype", [(32, 17, "f64"), (32, 17, "f32"), (35, 18, "f32")])
 def test_sigma_mirrored_full_size_sampled(torch_cuda, pdg, oracle_mod, om, n, dtype):
     """n > Omega/2 at full size: the mirrored kernel (holes as particles,
