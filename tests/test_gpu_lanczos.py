@@ -311,6 +311,42 @@ def test_full_size_mixed_ground_state_sampled(pdg, oracle_mod):
     np.testing.assert_allclose(r.occ, f.occ, atol=1e-7)
 
 
+def test_full_size_mirrored_mixed_sampled(pdg, oracle_mod):
+    """More pairs than half the orbits at full size: Omega=32, n=17 (5.66e8
+    states; the products run in the mirrored space, FP64 restart products on
+    the per-XCD chunk schedule), seed-0 instance, random start, tol 1e-10,
+    mixed precision.  The eigen-equation on sampled rows with the oracle's hop
+    enumeration, the Perron-Frobenius sign, the norm, sum <N_i> = 2n with
+    0 <= <N_i> <= 2, and E0 below the smallest diagonal element."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+    om, n = 32, 17
+    _, _, eps, V = inputs.c5_instance(om, n, seed=0)
+    assert (V < 0).all() and n > om - n
+    b = pdg.Basis(om, n, store_states=False)
+    print("full-size mixed solve omega=32 n=17 (mirrored)", flush=True)
+    r = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=1, precision="f32")
+    assert r.converged and r.residual <= 1e-10 and r.iterations_f32 > 0
+    psi = r.psi
+    assert int((psi < -1e-6 * float(psi.abs().max())).sum()) == 0
+    assert abs(float(psi.norm()) - 1.0) <= 1e-12
+    rng = np.random.default_rng(13)
+    rows = np.unique(np.concatenate([rng.integers(0, b.dim, 2000), np.arange(0, 100),
+                                     np.arange(b.dim - 100, b.dim)]))
+    diag, tg, cf = oracle_mod.row_terms(om, n, eps, V, rows)
+    pr = psi[torch.tensor(rows, device=psi.device)].cpu().numpy()
+    pt = psi[torch.tensor(tg.reshape(-1), device=psi.device)].cpu().numpy().reshape(tg.shape)
+    hpsi = diag * pr + (cf * pt).sum(axis=1)
+    assert np.all(np.abs(hpsi - r.E0 * pr) <= r.residual * abs(r.E0) + 1e-13)
+    assert abs(r.occ.sum() - 2 * n) <= 1e-8 and r.occ.min() >= 0.0 and r.occ.max() <= 2.0
+    assert r.E0 <= oracle_mod.monopole_min(om, n, eps, V)
+    r.psi = None
+    del psi
+    torch.cuda.empty_cache()
+
+
 def test_full_size_omega34_mixed_sampled(pdg, oracle_mod):
     """The large mixed-precision configuration: Omega=34, n=17 (2,333,606,220
     states, above 2^31: 64-bit loop indices in every vector kernel), seed-0
