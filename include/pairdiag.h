@@ -169,6 +169,17 @@ pd_status pd_basis_truncation(pd_basis b, int *truncated, int64_t *full_dim);
 pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
                    const void *x_dev, void *y_dev, hipStream_t stream);
 
+/* Launch shape of pd_sigma on the space (omega, n) in precision dt, without
+ * running anything (an implementation detail, not a passage of the paper):
+ * *threads = threads per workgroup (256 or 512), *lds_bytes = its dynamic
+ * LDS, *lds_limit_bytes = the LDS limit the kernel runs under (the
+ * instantiation's attribute above the default 64 KB, else that default);
+ * pd_sigma's launch succeeds only when lds_bytes <= lds_limit_bytes.  Host
+ * only, no device needed.  PD_EINVAL: bad space, dtype or NULL output;
+ * PD_ERANGE: min(n, omega - n) above the largest kernel's pair count. */
+pd_status pd_sigma_launch_shape(int omega, int n, pd_dtype dt, int *threads, int64_t *lds_bytes,
+                                int64_t *lds_limit_bytes);
+
 /* ------------------------------------------------------------------ Lanczos
  * Restarted, fully reorthogonalised Lanczos (Sec. 3.4, Alg. lanczos): Krylov
  * vectors are orthogonalised against all stored vectors (classical

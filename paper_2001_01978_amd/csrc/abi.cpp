@@ -851,6 +851,18 @@ pd_status pd_mlp_adam(int64_t count, float *params_dev, const float *grads_dev, 
     return PD_OK;
 }
 
+pd_status pd_sigma_launch_shape(int omega, int n, pd_dtype dt, int *threads, int64_t *lds_bytes,
+                                int64_t *lds_limit_bytes) {
+    if (!threads || !lds_bytes || !lds_limit_bytes) return fail(PD_EINVAL, "an output pointer is NULL");
+    if (!valid_space(omega, n)) return fail(PD_EINVAL, "invalid space omega=%d n=%d", omega, n);
+    if (dt != PD_F64 && dt != PD_F32) return fail(PD_EINVAL, "bad dtype %d", (int)dt);
+    const int nn = std::min(n, omega - n);
+    if (nn > kMaxSigmaPairs) return fail(PD_ERANGE, "min(n, omega-n)=%d exceeds %d", nn, kMaxSigmaPairs);
+    if (!sigma_launch_shape(omega, n, dt, threads, lds_bytes, lds_limit_bytes))
+        return fail(PD_ERANGE, "no product kernel for %d pairs", nn);
+    return PD_OK;
+}
+
 int64_t pd_stream_probe_bytes(int kind, int64_t n) {
     if (n <= 0) return 0;
     switch (kind & ~PD_PROBE_NONTEMPORAL) {

@@ -142,6 +142,9 @@ constexpr int kMaxSigmaPairs = 20;
 // sigma.hip: y = H x for dtype dt using coefficients at coef (device).
 // dsum64/dsum32: sum of all pair energies d_i (host copy of the block's dsum).
 // tr: nullptr for the full space, else the truncated space (dim = tr->kept).
+// Threads per workgroup, dynamic LDS and LDS limit of the product on a space
+// (false when min(n, omega - n) has no kernel).
+bool sigma_launch_shape(int omega, int n, pd_dtype dt, int *threads, int64_t *lds, int64_t *limit);
 hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd_dtype dt,
                         const void *x, void *y, hipStream_t s, double dsum64, float dsum32,
                         const TruncSpace *tr = nullptr);

@@ -1,6 +1,7 @@
 // Dispatch of y = H x to the kernel instantiations (rank width by dim, value
 // type by dtype); the kernels themselves are in sigma_impl.h.
 #include "pd_internal.h"
+#include "sigma_impl.h"
 
 namespace pd {
 
@@ -50,6 +51,24 @@ hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd
     const float *d = reinterpret_cast<const float *>(base + offsetof(CoefBlock, d32));
     const float *V = reinterpret_cast<const float *>(base + offsetof(CoefBlock, V32));
     return (small ? sigma_r32_f32 : sigma_r64_f32)(omega, n, dim, d, V, dsum32, (const float *)x, (float *)y, sched, s);
+}
+
+bool sigma_launch_shape(int omega, int n, pd_dtype dt, int *threads, int64_t *lds, int64_t *limit) {
+    const int nn = n > omega - n ? omega - n : n;
+    const bool small = binom_host(omega, n) < (uint64_t(1) << 32);
+    sigma_detail::LaunchShape sh{};
+    bool ok;
+    if (dt == PD_F64)
+        ok = small ? sigma_detail::shape_for<uint32_t, double>(omega, nn, &sh)
+                   : sigma_detail::shape_for<uint64_t, double>(omega, nn, &sh);
+    else
+        ok = small ? sigma_detail::shape_for<uint32_t, float>(omega, nn, &sh)
+                   : sigma_detail::shape_for<uint64_t, float>(omega, nn, &sh);
+    if (!ok) return false;
+    *threads = sh.threads;
+    *lds = (int64_t)sh.lds;
+    *limit = (int64_t)sh.limit;
+    return true;
 }
 
 }  // namespace pd

@@ -435,23 +435,55 @@ hipError_t launch_block(Params<R, T> P, size_t smem, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// The launch of a product: threads per workgroup, its dynamic LDS, and the
+// LDS limit the kernel then runs under (the instantiation's attribute when
+// the LDS exceeds the default 64 KB, else that default).
+struct LaunchShape {
+    int threads;
+    size_t lds;
+    size_t limit;
+};
+
 // Workgroups of 512 threads unless 256 keeps more waves resident: the LDS of
 // a workgroup is the tables plus 2 (NN + 1) rank words per thread, and 160 KB
 // per CU must hold whole workgroups.
-template <typename R, typename T, int NN, bool COMP>
-hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
-    const size_t tables = (table_bytes<R, T>(P.omega, P.ks) + 15) & ~size_t(15);
+template <typename R, typename T, int NN>
+LaunchShape choose_shape(int omega, int ks) {
+    const size_t tables = (table_bytes<R, T>(omega, ks) + 15) & ~size_t(15);
     const size_t s512 = tables + prefix_bytes<R>(NN, 512), s256 = tables + prefix_bytes<R>(NN, 256);
     const size_t waves512 = (kLdsUsable / s512) * 8, waves256 = std::min<size_t>((kLdsUsable / s256) * 4, 16);
+    const size_t kDefault = 64 * 1024;
+    if (waves256 > waves512) return {256, s256, s256 > kDefault ? lds_limit<R, T, NN, 256>() : kDefault};
+    return {512, s512, s512 > kDefault ? lds_limit<R, T, NN, 512>() : kDefault};
+}
+
+template <typename R, typename T, int NN, bool COMP>
+hipError_t launch_nn(const Params<R, T> &P, hipStream_t stream) {
+    const LaunchShape sh = choose_shape<R, T, NN>(P.omega, P.ks);
     // Byte-offset buffer gathers (FP32, every byte offset of x within 32 bits;
     // measured slower than 64-bit global loads for FP64 gathers).
     constexpr bool kCanBuf = sizeof(R) == 4 && sizeof(T) == 4;
     const bool buf = kCanBuf && (uint64_t)P.dim * sizeof(T) < (uint64_t(1) << 32);
-    if (waves256 > waves512)
-        return buf ? launch_block<R, T, NN, COMP, 256, kCanBuf>(P, s256, stream)
-                   : launch_block<R, T, NN, COMP, 256, false>(P, s256, stream);
-    return buf ? launch_block<R, T, NN, COMP, 512, kCanBuf>(P, s512, stream)
-               : launch_block<R, T, NN, COMP, 512, false>(P, s512, stream);
+    if (sh.threads == 256)
+        return buf ? launch_block<R, T, NN, COMP, 256, kCanBuf>(P, sh.lds, stream)
+                   : launch_block<R, T, NN, COMP, 256, false>(P, sh.lds, stream);
+    return buf ? launch_block<R, T, NN, COMP, 512, kCanBuf>(P, sh.lds, stream)
+               : launch_block<R, T, NN, COMP, 512, false>(P, sh.lds, stream);
+}
+
+// The shape launch_nn takes for a space with nn pairs in the working space.
+template <typename R, typename T>
+bool shape_for(int omega, int nn, LaunchShape *out) {
+    switch (nn) {
+#define PD_NN_CASE(K) \
+    case K: *out = choose_shape<R, T, K>(omega, K + 2); return true;
+        PD_NN_CASE(0) PD_NN_CASE(1) PD_NN_CASE(2) PD_NN_CASE(3) PD_NN_CASE(4) PD_NN_CASE(5) PD_NN_CASE(6)
+        PD_NN_CASE(7) PD_NN_CASE(8) PD_NN_CASE(9) PD_NN_CASE(10) PD_NN_CASE(11) PD_NN_CASE(12) PD_NN_CASE(13)
+        PD_NN_CASE(14) PD_NN_CASE(15) PD_NN_CASE(16) PD_NN_CASE(17) PD_NN_CASE(18) PD_NN_CASE(19)
+        PD_NN_CASE(20)
+#undef PD_NN_CASE
+        default: return false;
+    }
 }
 
 template <typename R, typename T, bool COMP>

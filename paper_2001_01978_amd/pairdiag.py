@@ -122,6 +122,7 @@ SIGNATURES = {
     "pd_lanczos_ground_static": (I, [P, P, P, ctypes.POINTER(LanczosOpts), P, ctypes.POINTER(D), P, P,
                                      ctypes.POINTER(LanczosInfo), P]),
     "pd_stream_probe_bytes": (I64, [I, I64]),
+    "pd_sigma_launch_shape": (I, [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
     "pd_stream_probe": (I, [I, P, P, P, I64, P]),
 }
 
@@ -202,6 +203,16 @@ def stream_probe(kind: str, a, b, c, nontemporal=False, stream=None) -> int:
     _check(L.pd_stream_probe(k, _dptr(a) if a is not None else None, _dptr(b) if b is not None else None, _dptr(c),
                              n, _stream(stream)))
     return int(L.pd_stream_probe_bytes(k, n))
+
+
+def sigma_launch_shape(omega: int, n: int, dtype="f64"):
+    """(threads per workgroup, dynamic LDS bytes, LDS limit bytes) of pd_sigma
+    on the space (omega, n) (pd_sigma_launch_shape; host only)."""
+    L = load()
+    t, lds, lim = I(), I64(), I64()
+    dt = PD_F32 if dtype in ("f32", PD_F32) else PD_F64
+    _check(L.pd_sigma_launch_shape(omega, n, dt, ctypes.byref(t), ctypes.byref(lds), ctypes.byref(lim)))
+    return int(t.value), int(lds.value), int(lim.value)
 
 
 def dimension(omega: int, n: int) -> int:

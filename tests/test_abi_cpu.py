@@ -161,3 +161,35 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_sigma_launch_shape_fits_its_limit_for_every_space():
+    """Every space with a product kernel (Omega <= 62, min(n, Omega - n) <=
+    20), in both precisions and both rank widths: the workgroup pd_sigma
+    launches asks for no more LDS than the kernel runs under, within the
+    160 KB of a CU less the static LDS.  (FP64 at Omega=35, n=17 once chose
+    512 threads at 162,864 bytes against a 162,816-byte limit.)"""
+    usable = 160 * 1024 - 1024
+    count = 0
+    for om in range(1, 63):
+        for n in range(om + 1):
+            if min(n, om - n) > 20:
+                continue
+            for dt in ("f64", "f32"):
+                t, lds, lim = pdg.sigma_launch_shape(om, n, dt)
+                assert t in (256, 512), (om, n, dt)
+                assert lds <= lim <= usable, (om, n, dt, t, lds, lim)
+                count += 1
+    assert count > 2500
+    assert pdg.sigma_launch_shape(35, 17, "f64")[0] == 256
+    assert pdg.sigma_launch_shape(32, 16, "f64")[0] == 512
+
+
+def test_sigma_launch_shape_errors():
+    L = pdg.load()
+    t, a, b = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+    assert L.pd_sigma_launch_shape(63, 2, 0, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b)) == 1   # PD_EINVAL
+    assert L.pd_sigma_launch_shape(20, 21, 0, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b)) == 1
+    assert L.pd_sigma_launch_shape(20, 10, 7, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b)) == 1
+    assert L.pd_sigma_launch_shape(20, 10, 0, None, ctypes.byref(a), ctypes.byref(b)) == 1
+    assert L.pd_sigma_launch_shape(62, 21, 0, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b)) == 2  # PD_ERANGE
