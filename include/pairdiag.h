@@ -355,12 +355,17 @@ pd_status pd_occupations(pd_basis b, const double *psi_dev, void *work_dev, size
  * batches of at most 32 instances, where the sample would be the whole batch,
  * take 512 untuned).  A cost model (work per product, team barrier overhead)
  * picks how many of the costliest instances are first solved by teams of
- * workgroups (8 teams of grid/8, grid = all compute units) that split the
- * rows and meet at a bounded-wait barrier; if a wait times out (another
- * kernel holding compute units) the call returns PD_EDEVICE.  Without teams
- * the grid is min(count, compute units).  The workspace holds one Krylov slot
- * per team sized for the largest instance and one per workgroup sized for the
- * largest instance left to single workgroups.  Returns PD_ENOCONV if any
+ * workgroups (grid = all compute units, split into 8 teams, or into the
+ * smallest power of two of teams that covers them when fewer than 5 instances
+ * go to teams) that split the rows and meet at a bounded-wait barrier; if a
+ * wait times out (another kernel holding compute units) the call returns
+ * PD_EDEVICE.  Without teams the grid is min(count, compute units).  The
+ * workspace holds one Krylov slot of (krylov + 2) x (largest dimension)
+ * doubles per team and one per workgroup sized for the largest instance left
+ * to single workgroups (pd_batched_workspace_bytes): a batch that sends 5 or
+ * more instances to teams, the largest of 2.26e8 states (omega = 32, 12
+ * pairs), needs 8 such slots, more than one device holds at krylov 20; solve
+ * such instances with pd_lanczos_ground.  Returns PD_ENOCONV if any
  * instance missed the tolerance (all outputs filled).  info_out[i].seconds is
  * the device time the instance took.
  * Synchronises `stream`. */

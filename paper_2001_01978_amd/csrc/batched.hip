@@ -526,8 +526,9 @@ double instance_cost(int omega, int n, int krylov) {
 }
 
 // Schedule: with a full grid (a multiple of 8 workgroups), 8 teams of grid/8
-// workgroups first solve the costliest instances (sorted order), then every
-// workgroup drains the rest alone.  Cost units are those of instance_cost
+// workgroups (fewer and larger ones when fewer than 5 instances go to teams)
+// first solve the costliest instances (sorted order), then every workgroup
+// drains the rest alone.  Cost units are those of instance_cost
 // (work of one product).  A team runs an instance at 93% of its workgroups'
 // combined rate plus a fixed overhead per product (its cross-workgroup
 // barriers): kTeamOverhead, about 57 us against the ~4e9 units/s of one
@@ -570,7 +571,17 @@ void plan_schedule(int count, const int *omega, const int *n, int krylov, int gr
             *n_large = split;
             break;
         }
-    if (*n_large > 0) *teams = nteams;
+    // Fewer large instances than teams: the fewest teams (a power of two, so
+    // it divides the grid) that still start every large instance at once;
+    // idle teams would only hold their slots.  Measured: one instance of
+    // 8.6e7 states 26.0 s on one of 8 teams of 32 workgroups, 3.9 s on one
+    // team of all 256 (and 122 -> 15 GB of workspace); two of 3.0e7 states
+    // 10.4 -> 2.8 s on two teams of 128.
+    if (*n_large > 0) {
+        int t = 1;
+        while (t < *n_large && t < nteams) t <<= 1;
+        *teams = t;
+    }
 }
 
 std::vector<int> cost_order(int count, const int *omega, const int *n, int krylov) {

@@ -82,7 +82,8 @@ def test_batched_team_and_single_workgroup_phases(pdg, oracle_mod):
     assert r.status == pdg.PD_OK and r.converged.all()
     if r.info["grid"] < 256:
         pytest.skip("fewer than 256 compute units: no team phase")
-    assert r.info["teams"] == 8 and 0 < r.info["large"] < len(insts), r.info
+    assert 0 < r.info["large"] < len(insts), r.info
+    assert r.info["teams"] == _teams_for(r.info["large"]), r.info
     dims = np.array([math.comb(i[0], i[1]) for i in insts])
     for q in np.argsort(-dims)[:4]:
         om, n, eps, V = insts[q]
@@ -96,22 +97,39 @@ def test_batched_team_and_single_workgroup_phases(pdg, oracle_mod):
         assert abs(r.E0[q] - e0) <= 1e-10 * abs(e0), (q, om, n)
 
 
+def _teams_for(large):
+    """Teams of the schedule: the smallest power of two not below the number
+    of instances that go to teams, at most 8."""
+    t = 1
+    while t < large and t < 8:
+        t *= 2
+    return t
+
+
 def test_batched_few_large_instances_use_the_whole_device(pdg):
     """Fewer instances than compute units, all large: teams spread them over
-    every workgroup slot of the device instead of one workgroup each; three
-    teams find no instance and go straight to the (empty) single phase."""
+    every workgroup slot of the device instead of one workgroup each; with 5
+    of them, 8 teams of an eighth of the grid (three find no instance and go
+    straight to the empty single phase), and a single instance runs on one
+    team of the whole grid."""
     insts = [inputs.family3_instance(9100 + s, omega=21, n=10) for s in range(5)]
     r = pdg.lanczos_ground_batched(insts, krylov=20, tol=1e-10, seed=7)
     assert r.status == pdg.PD_OK and r.converged.all()
     if r.info["grid"] < 64:
         pytest.skip("fewer than 64 compute units: no team phase")
     assert r.info["teams"] == 8 and r.info["large"] == len(insts), r.info
+    assert r.info["team_size"] * 8 == r.info["grid"]
     assert r.info["grid"] > len(insts) and r.info["tuned"] == 0 and r.info["block"] == 512
-    for q, (om, n, eps, V) in enumerate(insts):
+    one = [inputs.family3_instance(9150, omega=22, n=11)]
+    r1 = pdg.lanczos_ground_batched(one, krylov=20, tol=1e-10, seed=7)
+    assert r1.status == pdg.PD_OK and r1.converged.all()
+    assert r1.info["teams"] == 1 and r1.info["team_size"] == r1.info["grid"], r1.info
+    for q, (om, n, eps, V) in enumerate(insts + one):
         b = pdg.Basis(om, n, store_states=False)
         s = pdg.lanczos_ground(b, eps, V, krylov=20, tol=1e-10, start="random", seed=2, want_psi=False)
-        assert abs(r.E0[q] - s.E0) <= 1e-10 * abs(s.E0), (q, om, n)
-        assert np.allclose(r.occ[q], s.occ, atol=1e-8)
+        e, occ = (r.E0[q], r.occ[q]) if q < len(insts) else (r1.E0[0], r1.occ[0])
+        assert abs(e - s.E0) <= 1e-10 * abs(s.E0), (q, om, n)
+        assert np.allclose(occ, s.occ, atol=1e-8)
 
 
 def test_batched_edge_instances(pdg, oracle_mod):
