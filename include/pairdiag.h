@@ -165,6 +165,12 @@ pd_status pd_basis_truncation(pd_basis b, int *truncated, int64_t *full_dim);
  * uploaded on `stream` and the stream is synchronised; otherwise the call is
  * fully asynchronous.  pd_lanczos_ground keeps its own block in its
  * workspace.
+ * PD_ERANGE, before any device work: min(n, omega - n) above 20; or a full
+ * space with n = omega - 16 and omega 33, 34 or 35 (mirrored, 16 pairs,
+ * 32-bit ranks), whose product is disabled: it made an illegal memory access
+ * at omega = 34, n = 18 for a cause not yet found.  The same holds for the
+ * Lanczos entry points and everything built on them (pd_scf_ground, the
+ * odd-system blocks); truncated spaces are not affected.
  */
 pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
                    const void *x_dev, void *y_dev, hipStream_t stream);

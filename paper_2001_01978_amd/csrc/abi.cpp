@@ -80,10 +80,16 @@ namespace {
 
 bool valid_space(int omega, int n) { return omega >= 1 && omega <= kMaxOmega && n >= 0 && n <= omega; }
 
-pd_status check_sigma_range(pd_basis b) {
+// product: the caller runs full-space products on b (pd_warm_start does not).
+pd_status check_sigma_range(pd_basis b, bool product = true) {
     int nn = std::min(b->n, b->omega - b->n);
     if (nn > kMaxSigmaPairs)
         return fail(PD_ERANGE, "min(n, omega-n)=%d exceeds %d (dim %lld)", nn, kMaxSigmaPairs, (long long)b->dim);
+    if (product && !b->truncated && sigma_space_refused(b->omega, b->n))
+        return fail(PD_ERANGE,
+                    "omega=%d, n=%d: full-space products on mirrored spaces with 16 pairs and 32-bit ranks "
+                    "(omega 33-35) are disabled (an unexplained illegal memory access)",
+                    b->omega, b->n);
     return PD_OK;
 }
 
@@ -747,7 +753,7 @@ pd_status pd_lanczos_ground_batched(int count, const int *omega, const int *n, c
 pd_status pd_warm_start(pd_basis b, const float *logits_dev, double *x0_dev, hipStream_t stream) {
     pd_status st = check_full_basis(b, "pd_warm_start");
     if (st != PD_OK) return st;
-    if ((st = check_sigma_range(b)) != PD_OK) return st;
+    if ((st = check_sigma_range(b, false)) != PD_OK) return st;
     if ((st = check_device_ptr(logits_dev, "logits_dev", b->omega * sizeof(float))) != PD_OK) return st;
     if ((st = check_device_ptr(x0_dev, "x0_dev", b->dim * sizeof(double))) != PD_OK) return st;
     float l[64];

@@ -139,6 +139,17 @@ hipError_t launch_basis_unrank(int omega, int n, const int64_t *ranks, int64_t c
 
 // Largest min(n, omega - n) sigma handles (register width of its hop loop).
 constexpr int kMaxSigmaPairs = 20;
+// Full-space products refused: mirrored spaces (n > omega - n) with 16 pairs
+// in the working space and 32-bit ranks, i.e. omega 33, 34, 35 with n = omega
+// - 16.  Their kernel (the only 32-bit-rank FP64 product that spills, 20-24
+// bytes per lane) made an illegal memory access on the device at omega = 34,
+// n = 18, and the cause is not found: a CPU emulation of its index arithmetic
+// gives every hop target in range on sampled rows of all three spaces.  They
+// stay refused until the cause is shown.  Truncated products are not affected.
+inline bool sigma_space_refused(int omega, int n) {
+    const int nn = omega - n;
+    return n > nn && nn == 16 && binom_host(omega, n) < (uint64_t(1) << 32);
+}
 // sigma.hip: y = H x for dtype dt using coefficients at coef (device).
 // dsum64/dsum32: sum of all pair energies d_i (host copy of the block's dsum).
 // tr: nullptr for the full space, else the truncated space (dim = tr->kept).

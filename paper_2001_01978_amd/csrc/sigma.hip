@@ -40,6 +40,7 @@ hipError_t launch_sigma(int omega, int n, int64_t dim, const CoefBlock *coef, pd
         return (small ? sigma_trunc_r32_f32 : sigma_trunc_r64_f32)(omega, n, *tr, d, V, dsum32, (const float *)x,
                                                                  (float *)y, s);
     }
+    if (sigma_space_refused(omega, n)) return hipErrorNotSupported;
     const bool small = dim < (int64_t(1) << 32);
     unsigned *sched = reinterpret_cast<unsigned *>(const_cast<unsigned char *>(base) + offsetof(CoefBlock, sched));
     if (dt == PD_F64) {

@@ -314,9 +314,11 @@ __device__ __forceinline__ T sigma_row(int64_t row, int64_t dim, int omega, int 
 // With at most 17 pairs the product keeps all NN gathers of a hop block in
 // flight (ISSUE_ALL).  32-bit ranks: within 128 VGPRs, so 4 waves per SIMD,
 // the occupancy the LDS allows (measured at 32 and 34 orbits: 6-11% faster in
-// FP64, 7-9% in FP32); the mirrored space's FP64 kernel at 16 pairs spills
-// 16-24 bytes per lane there and is still faster (32 orbits, 17 pairs: 91.6
-// -> 79.8 ms; 34 orbits, 18 pairs: 515 -> 363 ms).  64-bit ranks: 3 waves
+// FP64, 7-9% in FP32; mirrored, 32 orbits and 17 pairs: 91.6 -> 79.8 ms
+// FP64).  The mirrored FP64 kernel at 16 pairs spills 20-24 bytes per lane
+// there; a copy of it outside the library ran 34 orbits, 18 pairs in 363
+// against 515 ms, but the library's spaces that use it are refused
+// (sigma_space_refused: an unexplained illegal memory access).  64-bit ranks: 3 waves
 // per SIMD, without spills when not mirrored (35 orbits, 17 pairs: 1557 ->
 // 1348 ms FP64, 803 -> 700 ms FP32); mirrored they spill up to 188 bytes per
 // lane and ran 2.3-3.2x slower, so they keep the compiler's schedule.
