@@ -102,12 +102,41 @@ PIPELINE = "sigma_omega{om}_n{n}_pipeline_counters"
 CLOCK_HZ, N_CU, N_SIMD = 2.4e9, 256, 1024
 
 
+def code_tokens(text):
+    """C++ source without its comments and with every run of whitespace
+    collapsed to one space (string and character literals kept whole), so
+    that an edit of comments or layout leaves the hash of the code alone."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 of the product kernel's code
+    (comments and layout excluded): the counter summaries carry the hash of
+    the source they were taken on."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -193,3 +193,21 @@ def test_sigma_launch_shape_errors():
     assert L.pd_sigma_launch_shape(20, 10, 7, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b)) == 1
     assert L.pd_sigma_launch_shape(20, 10, 0, None, ctypes.byref(a), ctypes.byref(b)) == 1
     assert L.pd_sigma_launch_shape(62, 21, 0, ctypes.byref(t), ctypes.byref(a), ctypes.byref(b)) == 2  # PD_ERANGE
+
+
+def test_bench_kernel_hash_ignores_comments_and_layout():
+    """The counter summaries are matched to the product kernel by a hash of
+    its code: comments and whitespace do not enter it, string literals and
+    every token of code do."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    a = "int f(int x) {  // first\n  return x + 1; /* two\n lines */ }\n"
+    b = "int f(int x) {\n\n    return x + 1;   }  // another\n"
+    assert bench.code_tokens(a) == bench.code_tokens(b) == "int f(int x) { return x + 1; }"
+    assert bench.code_tokens("s = \"a // b\"; c = '/'; // x") == "s = \"a // b\"; c = '/';"
+    assert bench.code_tokens(a.replace("x + 1", "x + 2")) != bench.code_tokens(a)
+    src = open(os.path.join(ROOT, "paper_2001_01978_amd", "csrc", "sigma_impl.h")).read()
+    assert bench.code_tokens(src) == bench.code_tokens(re.sub(r"//[^\n]*", "", src))
+    assert len(bench.kernel_source_hash()) == 16
