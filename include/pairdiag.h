@@ -180,8 +180,9 @@ pd_status pd_sigma(pd_basis b, const double *eps, const double *V, pd_dtype dt,
  * *threads = threads per workgroup (256 or 512), *lds_bytes = its dynamic
  * LDS, *lds_limit_bytes = the LDS limit the kernel runs under (the
  * instantiation's attribute above the default 64 KB, else that default);
- * pd_sigma's launch succeeds only when lds_bytes <= lds_limit_bytes.  Host
- * only, no device needed.  PD_EINVAL: bad space, dtype or NULL output;
+ * pd_sigma's launch succeeds only when lds_bytes <= lds_limit_bytes.  The
+ * shape is reported for the spaces pd_sigma refuses too.  Host only, no
+ * device needed.  PD_EINVAL: bad space, dtype or NULL output;
  * PD_ERANGE: min(n, omega - n) above the largest kernel's pair count. */
 pd_status pd_sigma_launch_shape(int omega, int n, pd_dtype dt, int *threads, int64_t *lds_bytes,
                                 int64_t *lds_limit_bytes);
