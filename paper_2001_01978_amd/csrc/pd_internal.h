@@ -143,9 +143,11 @@ constexpr int kMaxSigmaPairs = 20;
 // in the working space and 32-bit ranks, i.e. omega 33, 34, 35 with n = omega
 // - 16.  Their kernel (the only 32-bit-rank FP64 product that spills, 20-24
 // bytes per lane) made an illegal memory access on the device at omega = 34,
-// n = 18, and the cause is not found: a CPU emulation of its index arithmetic
-// gives every hop target in range on sampled rows of all three spaces.  They
-// stay refused until the cause is shown.  Truncated products are not affected.
+// n = 18, and the cause is not found: the row code, compiled for the host with
+// every array it reads against an inaccessible page, touches nothing outside
+// them on any row of the three spaces, so what remains is the compiled kernel
+// or its launch.  They stay refused until the cause is shown.  Truncated
+// products are not affected.
 inline bool sigma_space_refused(int omega, int n) {
     const int nn = omega - n;
     return n > nn && nn == 16 && binom_host(omega, n) < (uint64_t(1) << 32);
