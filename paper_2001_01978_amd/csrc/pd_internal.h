@@ -141,8 +141,8 @@ hipError_t launch_basis_unrank(int omega, int n, const int64_t *ranks, int64_t c
 constexpr int kMaxSigmaPairs = 20;
 // Full-space products refused: mirrored spaces (n > omega - n) with 16 pairs
 // in the working space and 32-bit ranks, i.e. omega 33, 34, 35 with n = omega
-// - 16.  Their kernel (the only 32-bit-rank FP64 product that spills, 20-24
-// bytes per lane) made an illegal memory access on the device at omega = 34,
+// - 16.  Their FP64 kernel (the library's only kernel that uses scratch: it
+// spills 20-24 bytes per lane) made an illegal memory access on the device at omega = 34,
 // n = 18, and the cause is not found: the row code, compiled for the host with
 // every array it reads against an inaccessible page, touches nothing outside
 // them on any row of the three spaces, so what remains is the compiled kernel
